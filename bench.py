@@ -1,0 +1,298 @@
+#!/usr/bin/env python3
+"""Benchmark of the TreeRay/RadPressure hot path on one MI355X.
+
+One step = the whole path over one synthetic cloud with inputs resident in HBM:
+tree build (b-nodes, h-nodes, centres of luminosity) -> ray tracing (walk, mapping,
+integration, finalisation, u_rad) -> radiation-pressure force -> dust equilibrium with
+the learned Newton guess.  Prints one JSON line.
+
+Default workload: the 128^3 collapsing core (150 Msun in (0.4 pc)^3, rho ~ r^-2 times a
+sigma = 1 lognormal field, T_gas log-uniform 10-300 K), N_side = 4 (192 rays),
+opening angle 1/8.  The guess network is trained before timing on another realisation
+of the same cloud (seed 1), on the GPU, with labels from the library's bracketed solve.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "core128": "128^3 collapsing core (0.4 pc, 150 Msun, rho ~ r^-2 x lognormal sigma=1), "
+               "T_gas 10-300 K, kappa = kappa_P(T_d), N_side=4 (192 rays), theta=1/8, "
+               "dust equilibrium with learned guess",
+    "turb64": "64^3 lognormal turbulent box (sigma_ln=1.5, k^-4), kappa 0.1-10, one star, "
+              "N_side=2 (48 rays), theta=1/4, code units",
+    "sphere16": "16^3 uniform sphere, N_side=1 (12 rays), theta=1/2, code units",
+    "amr256": "AMR 256^3-equivalent (64^3 base, 2 extra levels, ~2.5M leaves), 10 stars, "
+              "N_side=4 (192 rays), theta=1/8, dust equilibrium with learned guess",
+}
+
+B_LEAF, B_HNODE = 12, 36   # algorithmic bytes per accepted b-node / visited h-node
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2204_09072_amd", "csrc", "trace.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def make_workload(name, seed=0):
+    import workloads as W
+    if name == "core128":
+        return W.c3_core128(seed=seed)
+    if name == "turb64":
+        return W.c2_turb64(seed=seed)
+    if name == "sphere16":
+        return W.c1_sphere16()
+    if name == "amr256":
+        return W.c5_amr256(seed=seed)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def train_network(T, ctx, name, steps):
+    """Guess network trained on another realisation of the workload (untimed setup)."""
+    import torch
+    from paper_2204_09072_amd.guess import train_guess
+    from paper_2204_09072_amd.run import dust, trace, upload
+    import workloads as W
+    w = make_workload(name, seed=1)
+    dev = upload(w)
+    tree, J, F, U = trace(ctx, w, dev)
+    ctx.sync()
+    rho = dev["rho"]
+    tg = dev["t_gas"]
+    # 20 % log-uniform augmentation over the same ranges
+    n_aug = w.n_cells // 4
+    aug = W.dust_samples(n_aug, seed=7, rho_range=(float(w.rho.min()), float(w.rho.max())),
+                         u_range=(max(float(U.min()), 1e-30), float(U.max())),
+                         t_range=(10.0, 300.0)).astype(np.float32)
+    r_all = torch.cat([rho, torch.from_numpy(aug[:, 0]).cuda()])
+    u_all = torch.cat([U, torch.from_numpy(aug[:, 1]).cuda()])
+    t_all = torch.cat([tg, torch.from_numpy(aug[:, 2]).cuda()])
+    Td, _ = dust(ctx, r_all, u_all, t_all, w.units[0], w.units[1])
+    ctx.sync()
+    tree.free()
+    mlp, losses = train_guess(ctx, r_all.cpu().numpy(), u_all.cpu().numpy(), t_all.cpu().numpy(),
+                              Td.cpu().numpy(), steps=steps, log_every=max(steps // 5, 1))
+    return mlp, losses
+
+
+def cpu_baseline(w, n_pix, stride, u_rad=None):
+    """FP64 oracle on the host cores: tree, every `stride`-th target, force and dust."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    ot = oracle.Tree(w)
+    t_tree = time.perf_counter() - t0
+    cells = np.arange(0, w.n_cells, stride, dtype=np.int64)
+    t0 = time.perf_counter()
+    J, F = ot.trace(oracle.params(w.n_side, theta=w.theta), cells=cells, n_threads=threads)
+    t_trace = time.perf_counter() - t0
+    t_dust = 0.0
+    if w.cgs and w.t_gas is not None:
+        m = min(w.n_cells, 200_000)
+        rho = w.rho[:m].astype(np.float64)
+        u = np.full(m, 1e-10) if u_rad is None else np.asarray(u_rad[:m], np.float64)
+        t0 = time.perf_counter()
+        oracle.dust_eq(rho, u, w.t_gas[:m].astype(np.float64), w.units[0], w.units[1], 3.8e-33)
+        t_dust = (time.perf_counter() - t0) * w.n_cells / m
+    t_step = t_tree + t_trace * (w.n_cells / len(cells)) + t_dust
+    return {
+        "value": w.n_cells * n_pix / t_step,
+        "unit": "target-ray evaluations/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"FP64 oracle: full tree build ({t_tree:.2f} s), ray tracing of every "
+                   f"{stride}th target ({len(cells)} targets, {t_trace:.2f} s) scaled to all "
+                   f"{w.n_cells} targets, dust equilibrium timed on {min(w.n_cells, 200_000)} cells "
+                   f"and scaled; estimated step {t_step:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="core128", choices=sorted(WORKLOADS))
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--cpu-stride", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bins-per-pass", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2204_09072_amd as T
+    from paper_2204_09072_amd.run import params_of, upload
+
+    w = make_workload(args.workload)
+    n_pix = 12 * w.n_side * w.n_side
+    ctx = T.Context(0)
+    dev = upload(w)
+    log(f"workload {args.workload}: {w.n_cells} cells, {n_pix} rays")
+
+    mlp = None
+    train_info = None
+    if w.cgs:
+        t0 = time.perf_counter()
+        mlp, losses = train_network(T, ctx, args.workload, args.train_steps)
+        train_info = {"steps": args.train_steps, "seconds": round(time.perf_counter() - t0, 2),
+                      "loss": [round(l, 6) for _, l in losses]}
+        log("guess network trained", train_info)
+
+    p = params_of(w, bins_per_pass=args.bins_per_pass, blocks_per_cu=args.blocks_per_cu,
+                  chunk=args.chunk)
+    n = w.n_cells
+    J = torch.empty(n, device="cuda")
+    F = torch.empty((3, n), device="cuda")
+    U = torch.empty(n, device="cuda")
+    A = torch.empty((3, n), device="cuda")
+    PS = torch.empty(n, device="cuda")
+    TD = torch.empty(n, device="cuda")
+    IT = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dp = T.dust_params(w.units[0], w.units[1])
+
+    ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+          for k in ("build", "trace", "force", "dust")}
+    times = {k: [] for k in ev}
+
+    def step(record):
+        e = ev if record else None
+        if e: e["build"][0].record()
+        tree = T.build_tree(ctx, w.nb, w.max_level, w.blocks, w.x0, w.box_len, dev["rho"],
+                            dev["kappa"], dev["t_dust"], w.stars, w.units[0], w.units[1])
+        if e: e["build"][1].record(); e["trace"][0].record()
+        T.trace_rays(ctx, tree, p, J, F, U)
+        if e: e["trace"][1].record(); e["force"][0].record()
+        T.rad_force(ctx, tree, F, A, PS)
+        if e: e["force"][1].record()
+        if w.cgs:
+            if e: e["dust"][0].record()
+            T.dust_equilibrium(ctx, dev["rho"], U, dev["t_gas"], dp, TD, IT, mlp)
+            if e: e["dust"][1].record()
+        return tree
+
+    for i in range(args.warmup):
+        step(False).free()
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    trees = []
+    for i in range(args.steps):
+        tr = step(True)
+        torch.cuda.synchronize()
+        for k in ev:
+            if k == "dust" and not w.cgs:
+                continue
+            times[k].append(ev[k][0].elapsed_time(ev[k][1]))
+        trees.append(tr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    for tr in trees[:-1]:
+        tr.free()
+    tree = trees[-1]
+    ms = (t1 - t0) * 1000.0 / args.steps
+    value = n * n_pix / (ms / 1000.0)
+
+    # roofline of the dominant kernel (the ray-tracing walk)
+    cnt = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
+    T.walk_counts(ctx, tree, params_of(w), cnt)
+    ctx.sync()
+    c = cnt.to(torch.int64).sum(0).cpu().numpy()
+    alg_bytes = float(B_LEAF * c[0] + B_HNODE * (c[1] + c[2]))
+    t_trace = float(np.mean(times["trace"])) / 1000.0
+    achieved = alg_bytes / t_trace / 1e9
+    traffic = None
+    tj = os.path.join(ROOT, "profiles", f"trace_{args.workload}_traffic.json")
+    if os.path.exists(tj):
+        with open(tj) as f:
+            tr_info = json.load(f)
+        if tr_info.get("trace_hip_sha") == kernel_source_hash():
+            traffic = tr_info.get("bytes_per_launch")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 4), "traffic": traffic,
+            "kernel": "k_trace", "algorithmic_bytes_per_launch": alg_bytes,
+            "kernel_ms": round(t_trace * 1000, 3),
+            "walk_totals": {"b_nodes_accepted": int(c[0]), "h_nodes_accepted": int(c[1]),
+                            "h_nodes_opened": int(c[2])}}
+
+    # dust: learned vs plain guess at the same stopping rule, judged by the plain solve
+    dust = None
+    if w.cgs:
+        TP = torch.empty(n, device="cuda")
+        ITP = torch.empty(n, dtype=torch.uint8, device="cuda")
+        def timed(m, out, it, reps=20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            T.dust_equilibrium(ctx, dev["rho"], U, dev["t_gas"], dp, out, it, m)
+            e0.record()
+            for _ in range(reps):
+                T.dust_equilibrium(ctx, dev["rho"], U, dev["t_gas"], dp, out, it, m)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+        ms_plain = timed(None, TP, ITP)
+        ms_learned = timed(mlp, TD, IT)
+        err = (TD - TP).abs() / TP
+        dust = {"unit": "T_dust solves/s",
+                "learned_solves_per_s": n / (ms_learned / 1000.0),
+                "plain_solves_per_s": n / (ms_plain / 1000.0),
+                "speedup_learned_over_plain": round(ms_plain / ms_learned, 3),
+                "max_rel_diff_learned_vs_plain": float(err.max().item()),
+                "mean_newton_iters_learned": float(IT.float().mean().item()),
+                "mean_newton_iters_plain": float(ITP.float().mean().item()),
+                "stop_rule": "|dT| <= 1e-6 T or residual at rounding level, bracket-safeguarded",
+                "network": train_info}
+
+    base = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        base = cpu_baseline(w, n_pix, args.cpu_stride, U.cpu().numpy())
+
+    out = {
+        "metric": "target-ray evaluations/s + T_dust solves/s, learned vs plain at fixed error",
+        "value": value,
+        "unit": "target-ray evaluations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+                   "n_cells": n, "n_pix": n_pix, "n_bins": tree.n_bins, "n_nodes": tree.n_node,
+                   "bins_per_pass": args.bins_per_pass, "parallelism": "single GPU"},
+        "kernels_ms": {k: round(float(np.mean(v)), 3) for k, v in times.items() if v},
+        "dust": dust,
+        "roofline": roof,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+    tree.free()
+
+
+if __name__ == "__main__":
+    main()

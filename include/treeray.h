@@ -1,0 +1,191 @@
+/*
+ * treeray.h -- C ABI of the MI355X (gfx950) TreeRay/RadPressure hot path.
+ *
+ * The library computes, for every cell of an AMR grid, the diffuse infrared radiation
+ * field of Klepitko et al. (MNRAS 2023, "Tree-based solvers for adaptive mesh refinement
+ * code FLASH - III"): every cell and every star particle is a source; rays from each
+ * target cell are HEALPix pixels; octree nodes are mapped onto radial ray segments and
+ * each ray is integrated in 1-D (Sec. 4).  Outputs are the fields the paper names:
+ * mean intensity J (IRXE), flux F, radiation-pressure acceleration a_RP (RPAX/Y/Z),
+ * trapped source pressure P_src (PRAD) and the dust temperature (TDUS) (Sec. 4).
+ *
+ * Conventions
+ *  - All functions return an int status: TR_OK or a negative TR_E* code; the message of
+ *    the last failure on a context is returned by tr_last_error().  No exception crosses
+ *    the ABI.
+ *  - "device" pointers are HIP device memory owned by the caller; the library never frees
+ *    them.  "host" pointers are read during the call only.  Handles (tr_ctx, tr_tree,
+ *    tr_mlp) are owned by the library and released by their *_free / *_destroy call.
+ *  - Work is enqueued on the context's stream; calls return before the GPU finishes
+ *    unless stated otherwise.  Device-side failures (stack overflow in the tree walk)
+ *    are latched in the context and reported by tr_sync().
+ *  - Cell arrays are block-major in the order of the grid's block list; inside a block of
+ *    8^3 cells the cell (ci, cj, ck) has local offset ci + 8 cj + 64 ck.  Vector outputs
+ *    are structure-of-arrays: F[0..n) = F_x, F[n..2n) = F_y, F[2n..3n) = F_z.
+ *  - Units: cgs, or code units with sigma = pi and c = 1; the library uses only the
+ *    sigma and c given in tr_units and the lengths given in tr_grid.
+ */
+#ifndef TREERAY_H
+#define TREERAY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TR_OK = 0,
+    TR_EINVAL = -1,    /* bad argument or grid (message says which) */
+    TR_ENOMEM = -2,    /* device or host allocation failed */
+    TR_EHIP = -3,      /* a HIP runtime call failed */
+    TR_EOVERFLOW = -4, /* the walk's per-wave stack overflowed (results invalid) */
+};
+
+typedef struct tr_ctx tr_ctx;
+typedef struct tr_tree tr_tree;
+typedef struct tr_mlp tr_mlp;
+
+/* AMR grid: a cubic domain of nb^3 base blocks, each leaf block of 8^3 cells at a
+ * refinement level 0..max_level (level l has cell edge box_len / (8 nb 2^l)).
+ * blocks is a HOST array [n_blk][4] = (level, bi, bj, bk), bi..bk in [0, nb 2^level).
+ * Leaf blocks must tile the domain without overlap. */
+typedef struct tr_grid {
+    int32_t nb;
+    int32_t max_level;
+    int32_t n_blk;
+    const int32_t *blocks;
+    double x0[3];
+    double box_len;
+} tr_grid;
+
+typedef struct tr_units {
+    double sigma; /* Stefan-Boltzmann constant in the caller's units */
+    double c;     /* speed of light */
+} tr_units;
+
+/* point source with non-ionising luminosity L_IR (Sec. 4.1.1); host array */
+typedef struct tr_star {
+    double x, y, z, L;
+} tr_star;
+
+/* Tree build (Sec. 4.1 b-nodes; App. A h-nodes and centre of luminosity).
+ * rho, t_dust: device float[n_cells]; kappa: device float[n_cells] or NULL, in which
+ * case the Planck-mean dust opacity of t_dust is used (Sec. 2).  A cell is optically
+ * thick when rho kappa dx >= 1.  The star host cell is the leaf containing (x, y, z)
+ * with half-open cells.  Synchronises the stream once (to size the node arrays).
+ * The tree keeps per-cell opacity and optical depth for tr_rad_force. */
+int tr_build_tree(tr_ctx *ctx, const tr_grid *grid, const float *rho, const float *kappa,
+                  const float *t_dust, const tr_star *stars, int n_stars,
+                  const tr_units *units, tr_tree **out);
+void tr_tree_free(tr_tree *tree);
+
+typedef struct tr_tree_info {
+    int64_t n_node, n_leaf, n_cells;
+    int32_t depth;     /* depth of the finest cells (root = 0) */
+    int32_t root_edge; /* root edge in lattice units u = half the finest cell edge */
+    int32_t n_bins;    /* ray evaluation points R_i = i^2 u, i = 1..n_bins */
+    double u_len;      /* u in length units */
+} tr_tree_info;
+int tr_tree_get_info(const tr_tree *tree, tr_tree_info *info);
+
+/* Copy the node arrays to HOST buffers (any may be NULL); synchronous.  Node order:
+ * by depth, then Morton order of the node's integer coordinates; children of a node are
+ * consecutive.  geo[n][4] = (centre x, y, z in u, first child or -1); meta[n] = depth |
+ * child mask << 4 | leaf << 12; q[n][4] = leaf (L, A, S, 0) with the sign bit of L set
+ * for optically thick leaves, h-node (L_thin, L_thick*V_thick, A_thin, A_thick);
+ * vthick[n]; pcol[n][3] = mapping position in u/256; leaf_cell[n] = cell or -1.
+ * Luminosities are in (length unit / u)^2 times the caller's units, areas in u^2. */
+int tr_tree_export(tr_ctx *ctx, const tr_tree *tree, int32_t *geo, uint32_t *meta,
+                   float *q, float *vthick, int32_t *pcol, int64_t *leaf_cell);
+
+/* Ray tracing parameters (Sec. 4.2-4.4). */
+typedef struct tr_trace_params {
+    int32_t n_side;        /* HEALPix N_side: 1, 2, 4 or 8 (12 N_side^2 rays) */
+    int32_t theta_num;     /* opening angle theta = num/den; 0/0 selects 1/(2 N_side) */
+    int32_t theta_den;
+    int32_t cube_m;        /* direction cells per cube-face edge of the angular kernel;
+                              0 selects 16 N_side */
+    int32_t merge;         /* 1: merge segments spanned by thick material (Sec. 4.3) */
+    float j_bg;            /* background intensity entering at the ray ends */
+    int32_t bins_per_pass; /* ray segments held in LDS per walk pass; 0 = automatic */
+    int32_t chunk;         /* targets taken per work-queue grab; 0 = automatic */
+    int32_t blocks_per_cu; /* persistent blocks per compute unit; 0 = automatic */
+} tr_trace_params;
+
+/* Trace all cells of the tree: J (device float[n_cells], IRXE), F (device float[3][n],
+ * flux), u_rad (device float[n_cells] = 4 pi J / c, or NULL).  Asynchronous; graph
+ * capturable after the first call with the same N_side and cube_m (the first call builds
+ * the angular-kernel table). */
+int tr_trace_rays(tr_ctx *ctx, const tr_tree *tree, const tr_trace_params *p, float *J,
+                  float *F, float *u_rad);
+
+/* Walk statistics of the opening-angle walk per target cell: counters (device
+ * int32[n_cells][3] = b-nodes accepted, h-nodes accepted, h-nodes opened). */
+int tr_walk_counts(tr_ctx *ctx, const tr_tree *tree, const tr_trace_params *p,
+                   int32_t *counters);
+
+/* Angular kernel table [6][M][M] (pixel id of each direction cell) and ray directions
+ * [N_pix][3], built on the device and copied to HOST buffers; synchronous. */
+int tr_ray_tables(tr_ctx *ctx, int n_side, int cube_m, int32_t *table, float *dirs);
+
+/* Radiation pressure (Sec. 4.5): a_RP = kappa F / c (1 - e^-tau)/tau with the factor 1
+ * below tau = 1e-4, tau = rho kappa dx of the cell; P_src = (1 - e^{-tau/2}) L / (c dV^(2/3))
+ * in cells hosting stars, 0 elsewhere.  F: device float[3][n]; a_rp: device
+ * float[3][n]; p_src: device float[n] or NULL. */
+int tr_rad_force(tr_ctx *ctx, const tr_tree *tree, const float *F, float *a_rp,
+                 float *p_src);
+
+/* Dust thermal equilibrium (Sec. 4.6, App. E).  Balance of thermal emission
+ * xi 4 sigma rho kappa(T_d) T_d^4, absorption xi 4 pi rho kappa(T_J) J and gas-dust
+ * collisional coupling c_gd n_H^2 sqrt(T_g) (T_g - T_d) (1 - 0.8 exp(-75/T_g)),
+ * n_H = rho / (1.4 m_H); floor 2.7 K.  The root is unique and is found by Newton's
+ * method inside a sign-changing bracket, falling back to bisection. */
+typedef struct tr_dust_params {
+    double sigma, c;
+    double c_gd;      /* gas-dust coupling coefficient (erg s^-1 cm^3 K^-3/2) */
+    double xi;        /* factor on the radiative rates (1 = kappa per gram of gas) */
+    float rel_tol;    /* Newton stop |dT| <= rel_tol T (0 selects 1e-6) */
+    int32_t max_iter; /* 0 selects 50 */
+} tr_dust_params;
+
+/* rho, u_rad, t_gas: device float[n]; t_dust: device float[n]; iters: device uint8[n]
+ * or NULL (Newton/bisection steps taken).  mlp: trained guess network or NULL for the
+ * plain start (the secant point of the bracket). */
+int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, const float *u_rad,
+                        const float *t_gas, const tr_dust_params *p, const tr_mlp *mlp,
+                        float *t_dust, uint8_t *iters);
+
+/* Guess network for the dust equilibrium: inputs (log10 rho, log10 u_rad, log10 T_gas)
+ * normalised as (v - shift) * scale, output log10 T_d = y / out_scale + out_shift;
+ * 3 -> 64 -> 64 -> 1 with tanh hidden layers; BF16 MFMA with FP32 accumulation.
+ * Parameters (HOST float, n = tr_mlp_n_params()) in the order
+ * W1[64][3] b1[64] W2[64][64] b2[64] W3[64] b3. */
+int tr_mlp_n_params(void);
+int tr_mlp_create(tr_ctx *ctx, const float *params_host, const float *norm_host /* [8]:
+                  shift[3], scale[3], out_shift, out_scale */, tr_mlp **out);
+void tr_mlp_free(tr_mlp *mlp);
+int tr_mlp_get_params(tr_ctx *ctx, const tr_mlp *mlp, float *params_host);
+/* Forward only: x device float[n][3] (already normalised) -> y device float[n]. */
+int tr_mlp_forward(tr_ctx *ctx, const tr_mlp *mlp, int64_t n, const float *x, float *y);
+/* Loss and gradients of the mean squared error for one batch: grad device
+ * float[n_params] (overwritten), loss device float[1]. */
+int tr_mlp_grad(tr_ctx *ctx, const tr_mlp *mlp, int64_t n, const float *x, const float *y,
+                float *grad, float *loss);
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the batch; loss device
+ * float[1] or NULL. */
+int tr_mlp_train_step(tr_ctx *ctx, tr_mlp *mlp, int64_t n, const float *x, const float *y,
+                      float lr, float *loss);
+
+/* Context: one HIP device and stream (hipStream_t passed as void*, NULL = null stream). */
+int tr_ctx_create(tr_ctx **out, int device, void *stream);
+void tr_ctx_destroy(tr_ctx *ctx);
+int tr_ctx_set_stream(tr_ctx *ctx, void *stream);
+const char *tr_last_error(const tr_ctx *ctx);
+/* Wait for the stream and report latched device-side failures (TR_EOVERFLOW). */
+int tr_sync(tr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

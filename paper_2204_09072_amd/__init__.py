@@ -1,0 +1,273 @@
+"""Python binding of the MI355X TreeRay/RadPressure library (libtreeray.so).
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels behind
+the C ABI declared in ``include/treeray.h``.  Device buffers are torch tensors on the
+HIP device (torch provides memory and streams); the library never sees torch types.
+Importing this module fails loudly when the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtreeray.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2204_09072_amd.build` "
+                      "(hipcc, gfx950)")
+
+_lib = C.CDLL(LIB_PATH)
+_P = C.c_void_p
+
+TR_OK, TR_EINVAL, TR_ENOMEM, TR_EHIP, TR_EOVERFLOW = 0, -1, -2, -3, -4
+
+
+class TreerayError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"treeray error {code}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("max_level", C.c_int32), ("n_blk", C.c_int32),
+                ("blocks", _P), ("x0", C.c_double * 3), ("box_len", C.c_double)]
+
+
+class Units(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("c", C.c_double)]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [("n_node", C.c_int64), ("n_leaf", C.c_int64), ("n_cells", C.c_int64),
+                ("depth", C.c_int32), ("root_edge", C.c_int32), ("n_bins", C.c_int32),
+                ("u_len", C.c_double)]
+
+
+class TraceParams(C.Structure):
+    _fields_ = [("n_side", C.c_int32), ("theta_num", C.c_int32), ("theta_den", C.c_int32),
+                ("cube_m", C.c_int32), ("merge", C.c_int32), ("j_bg", C.c_float),
+                ("bins_per_pass", C.c_int32), ("chunk", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+
+class DustParams(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("c", C.c_double), ("c_gd", C.c_double), ("xi", C.c_double),
+                ("rel_tol", C.c_float), ("max_iter", C.c_int32)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_I = C.c_int
+_sig("tr_ctx_create", _I, [C.POINTER(_P), _I, _P])
+_sig("tr_ctx_destroy", None, [_P])
+_sig("tr_ctx_set_stream", _I, [_P, _P])
+_sig("tr_last_error", C.c_char_p, [_P])
+_sig("tr_sync", _I, [_P])
+_sig("tr_build_tree", _I, [_P, C.POINTER(Grid), _P, _P, _P, _P, _I, C.POINTER(Units), C.POINTER(_P)])
+_sig("tr_tree_free", None, [_P])
+_sig("tr_tree_get_info", _I, [_P, C.POINTER(TreeInfo)])
+_sig("tr_tree_export", _I, [_P, _P, _P, _P, _P, _P, _P, _P])
+_sig("tr_trace_rays", _I, [_P, _P, C.POINTER(TraceParams), _P, _P, _P])
+_sig("tr_walk_counts", _I, [_P, _P, C.POINTER(TraceParams), _P])
+_sig("tr_ray_tables", _I, [_P, _I, _I, _P, _P])
+_sig("tr_rad_force", _I, [_P, _P, _P, _P, _P])
+_sig("tr_dust_equilibrium", _I, [_P, C.c_int64, _P, _P, _P, C.POINTER(DustParams), _P, _P, _P])
+_sig("tr_mlp_n_params", _I, [])
+_sig("tr_mlp_create", _I, [_P, _P, _P, C.POINTER(_P)])
+_sig("tr_mlp_free", None, [_P])
+_sig("tr_mlp_get_params", _I, [_P, _P, _P])
+_sig("tr_mlp_forward", _I, [_P, _P, C.c_int64, _P, _P])
+_sig("tr_mlp_grad", _I, [_P, _P, C.c_int64, _P, _P, _P, _P])
+_sig("tr_mlp_train_step", _I, [_P, _P, C.c_int64, _P, _P, C.c_float, _P])
+
+MLP_NPARAM = _lib.tr_mlp_n_params()
+MLP_HIDDEN = 64
+
+
+def _ptr(t):
+    """Device (or host numpy) address of a buffer, None for None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(_P)
+    return _P(t.data_ptr())
+
+
+class Context:
+    """One HIP device and stream (tr_ctx)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        self._torch = torch
+        h = _P()
+        s = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
+        rc = _lib.tr_ctx_create(C.byref(h), device, _P(s))
+        if rc:
+            raise TreerayError(rc, "tr_ctx_create failed")
+        self.h = h
+
+    def check(self, rc):
+        if rc:
+            raise TreerayError(rc, _lib.tr_last_error(self.h).decode())
+
+    def set_stream(self, stream):
+        self.check(_lib.tr_ctx_set_stream(self.h, _P(stream)))
+
+    def sync(self):
+        self.check(_lib.tr_sync(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.tr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Tree:
+    """Library-owned octree (tr_tree)."""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self.h = h
+        info = TreeInfo()
+        ctx.check(_lib.tr_tree_get_info(h, C.byref(info)))
+        self.n_node = info.n_node
+        self.n_leaf = info.n_leaf
+        self.n_cells = info.n_cells
+        self.depth = info.depth
+        self.root_edge = info.root_edge
+        self.n_bins = info.n_bins
+        self.u_len = info.u_len
+
+    def free(self):
+        if getattr(self, "h", None):
+            _lib.tr_tree_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.free()
+
+
+def build_tree(ctx: Context, nb, max_level, blocks, x0, box_len, rho, kappa, t_dust, stars,
+               sigma, c) -> Tree:
+    """tr_build_tree.  blocks: host int32 [n_blk, 4]; rho, kappa (or None), t_dust: device
+    float32 [n_cells]; stars: host float64 [n, 4]."""
+    blocks = np.ascontiguousarray(blocks, np.int32)
+    g = Grid(int(nb), int(max_level), int(blocks.shape[0]), _ptr(blocks),
+             (C.c_double * 3)(*[float(v) for v in x0]), float(box_len))
+    st = np.ascontiguousarray(np.asarray(stars, np.float64).reshape(-1, 4))
+    u = Units(float(sigma), float(c))
+    h = _P()
+    ctx.check(_lib.tr_build_tree(ctx.h, C.byref(g), _ptr(rho), _ptr(kappa), _ptr(t_dust),
+                                 _ptr(st) if st.shape[0] else None, int(st.shape[0]), C.byref(u),
+                                 C.byref(h)))
+    return Tree(ctx, h)
+
+
+def tree_export(ctx: Context, tree: Tree):
+    n = tree.n_node
+    out = dict(geo=np.zeros((n, 4), np.int32), meta=np.zeros(n, np.uint32),
+               q=np.zeros((n, 4), np.float32), vthick=np.zeros(n, np.float32),
+               pcol=np.zeros((n, 3), np.int32), leaf_cell=np.zeros(n, np.int64))
+    ctx.check(_lib.tr_tree_export(ctx.h, tree.h, *[_ptr(out[k]) for k in
+                                                   ("geo", "meta", "q", "vthick", "pcol", "leaf_cell")]))
+    return out
+
+
+def trace_params(n_side, theta=None, cube_m=0, merge=True, j_bg=0.0, bins_per_pass=0, chunk=0,
+                 blocks_per_cu=0) -> TraceParams:
+    th = (0, 0) if theta is None else theta
+    return TraceParams(int(n_side), int(th[0]), int(th[1]), int(cube_m), int(bool(merge)),
+                       float(j_bg), int(bins_per_pass), int(chunk), int(blocks_per_cu))
+
+
+def trace_rays(ctx: Context, tree: Tree, p: TraceParams, J, F, u_rad=None):
+    """tr_trace_rays: J [n], F [3, n], u_rad [n] or None (device float32)."""
+    ctx.check(_lib.tr_trace_rays(ctx.h, tree.h, C.byref(p), _ptr(J), _ptr(F), _ptr(u_rad)))
+
+
+def walk_counts(ctx: Context, tree: Tree, p: TraceParams, counters):
+    """tr_walk_counts: counters device int32 [n, 3]."""
+    ctx.check(_lib.tr_walk_counts(ctx.h, tree.h, C.byref(p), _ptr(counters)))
+
+
+def ray_tables(ctx: Context, n_side: int, cube_m: int = 0):
+    M = cube_m or 16 * n_side
+    tab = np.zeros(6 * M * M, np.int32)
+    dirs = np.zeros((12 * n_side * n_side, 3), np.float32)
+    ctx.check(_lib.tr_ray_tables(ctx.h, int(n_side), int(M), _ptr(tab), _ptr(dirs)))
+    return tab, dirs
+
+
+def rad_force(ctx: Context, tree: Tree, F, a_rp, p_src=None):
+    """tr_rad_force: F, a_rp [3, n]; p_src [n] or None (device float32)."""
+    ctx.check(_lib.tr_rad_force(ctx.h, tree.h, _ptr(F), _ptr(a_rp), _ptr(p_src)))
+
+
+def dust_params(sigma, c, c_gd=3.8e-33, xi=1.0, rel_tol=0.0, max_iter=0) -> DustParams:
+    return DustParams(float(sigma), float(c), float(c_gd), float(xi), float(rel_tol), int(max_iter))
+
+
+def dust_equilibrium(ctx: Context, rho, u_rad, t_gas, p: DustParams, t_dust, iters=None, mlp=None):
+    """tr_dust_equilibrium on device float32 arrays; iters uint8 or None."""
+    n = int(rho.numel())
+    ctx.check(_lib.tr_dust_equilibrium(ctx.h, n, _ptr(rho), _ptr(u_rad), _ptr(t_gas), C.byref(p),
+                                       None if mlp is None else mlp.h, _ptr(t_dust), _ptr(iters)))
+
+
+class Mlp:
+    """Guess network (tr_mlp): parameters W1[64][3] b1 W2[64][64] b2 W3[64] b3 (float32)."""
+
+    def __init__(self, ctx: Context, params: np.ndarray, norm=None):
+        self.ctx = ctx
+        prm = np.ascontiguousarray(params, np.float32)
+        assert prm.shape == (MLP_NPARAM,)
+        nrm = None if norm is None else np.ascontiguousarray(norm, np.float32)
+        h = _P()
+        ctx.check(_lib.tr_mlp_create(ctx.h, _ptr(prm), _ptr(nrm), C.byref(h)))
+        self.h = h
+        self.norm = nrm
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MLP_NPARAM, np.float32)
+        self.ctx.check(_lib.tr_mlp_get_params(self.ctx.h, self.h, _ptr(out)))
+        return out
+
+    def forward(self, x, y):
+        self.ctx.check(_lib.tr_mlp_forward(self.ctx.h, self.h, int(x.shape[0]), _ptr(x), _ptr(y)))
+
+    def grad(self, x, y, grad, loss):
+        self.ctx.check(_lib.tr_mlp_grad(self.ctx.h, self.h, int(x.shape[0]), _ptr(x), _ptr(y),
+                                        _ptr(grad), _ptr(loss)))
+
+    def train_step(self, x, y, lr, loss=None):
+        self.ctx.check(_lib.tr_mlp_train_step(self.ctx.h, self.h, int(x.shape[0]), _ptr(x), _ptr(y),
+                                              float(lr), _ptr(loss)))
+
+    def free(self):
+        if getattr(self, "h", None):
+            _lib.tr_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.free()
+
+
+def init_mlp_params(seed: int = 0) -> np.ndarray:
+    """Random initial parameters (uniform, fan-in scaled)."""
+    rng = np.random.default_rng(seed)
+    H = MLP_HIDDEN
+    parts = [rng.uniform(-1, 1, 3 * H) / np.sqrt(3), np.zeros(H),
+             rng.uniform(-1, 1, H * H) / np.sqrt(H), np.zeros(H),
+             rng.uniform(-1, 1, H) / np.sqrt(H), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)

@@ -1,0 +1,72 @@
+// Internal declarations shared by the library's HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "treeray.h"
+
+#define TR_FX 256 /* fixed-point subdivisions of the lattice unit (mapping positions) */
+#define TR_MAX_DEPTH 9
+
+struct RayTable {
+    int n_side = 0, cube_m = 0;
+    int16_t *table = nullptr; // [6][M][M] pixel ids
+    float4 *dirs = nullptr;   // [npix] unit vectors
+};
+
+struct tr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+    std::string err;
+    // device scratch: [0] work counter(s), [16] error word
+    int *d_ctl = nullptr;
+    std::map<std::pair<int, int>, RayTable> tables;
+    // pinned host word for reading back the error flag
+    int *h_err = nullptr;
+    // grow-only workspace for the dust solve's learned starting points
+    float *ws_guess = nullptr;
+    int64_t ws_guess_n = 0;
+};
+
+struct tr_tree {
+    tr_ctx *ctx = nullptr;
+    int nb = 0, max_level = 0, n_blk = 0, D = 0;
+    int64_t n_fine = 0, root_edge = 0, n_node = 0, n_leaf = 0, n_cells = 0;
+    int n_bins = 0;
+    double x0[3] = {0, 0, 0}, box_len = 0, u_len = 0, sigma = 0, c_light = 1;
+    int64_t depth_off[TR_MAX_DEPTH + 2] = {0};
+    // node arrays (SoA, node id order)
+    int4 *geo = nullptr;       // centre (u) and first child (-1 for leaves)
+    uint32_t *meta = nullptr;  // depth | mask << 4 | leaf << 12
+    float4 *q = nullptr;       // node content
+    float *vthick = nullptr;   // thick volume of h-nodes (u^3)
+    int4 *pcol = nullptr;      // mapping position (u / 256)
+    int32_t *leaf_cell = nullptr;
+    // per cell
+    int32_t *node_of_cell = nullptr;
+    int32_t *targets = nullptr;   // leaf node ids in node order
+    int32_t *target_cell = nullptr;
+    float *cell_tau = nullptr;    // rho kappa dx
+    float *cell_kappa = nullptr;
+    float *cell_src = nullptr;    // hosted star luminosity / u_len^2 (0 if none)
+};
+
+int tr_fail(tr_ctx *ctx, int code, const char *fmt, ...);
+
+#define TR_HIP(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return tr_fail((ctx), TR_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+int tr_get_table(tr_ctx *ctx, int n_side, int cube_m, RayTable **out);
+
+static inline int64_t tr_div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -1,0 +1,148 @@
+// Dust thermal equilibrium (Sec. 4.6 and App. E of Klepitko et al. 2023).
+//
+// Per cell, the residual divided by rho,
+//   g(T) = xi 4 sigma kappa(T) T^4 - xi 4 pi kappa(T_J) J - C (T_g - T),
+//   C    = c_gd rho / (1.4 m_H)^2 sqrt(T_g) (1 - 0.8 exp(-75 / T_g)),
+// is strictly increasing, negative at min(T_g, T_J) and positive at max(T_g, T_J).
+// Newton's method (on ln w against ln T, see the kernel) runs inside that bracket, with
+// bisection when a step leaves it; the starting point is the bracket's secant point in
+// logarithms, or the guess network's output.
+#include "common.hpp"
+#include "mlp.hpp"
+
+namespace {
+
+constexpr float kPiF = 3.14159265358979f;
+constexpr float kFloor = 2.7f;
+constexpr double kMH = 1.6735575e-24;
+
+__device__ __forceinline__ float kap_planck(float t) { return t < 150.0f ? 1.0e-3f * (t * t) : 22.5f; }
+// kappa(T) T^4 and its derivative
+__device__ __forceinline__ void emis(float t, float &v, float &dv) {
+    const float t2 = t * t, t4 = t2 * t2;
+    if (t < 150.0f) {
+        v = 1.0e-3f * t2 * t4;
+        dv = 6.0e-3f * t * t4;
+    } else {
+        v = 22.5f * t4;
+        dv = 90.0f * t * t2;
+    }
+}
+
+struct DustArgs {
+    int64_t n;
+    const float *rho, *u_rad, *t_gas;
+    float *t_dust;
+    uint8_t *iters;
+    float a4s;      // xi 4 sigma
+    float c_over_4pi;
+    float pi_over_sigma;
+    float xi4pi;
+    float cgd_n;    // c_gd / (1.4 m_H)^2
+    float tol;
+    int max_iter;
+    const float *guess; // learned starting points (NULL: plain start)
+};
+
+template <bool LEARNED>
+__global__ __launch_bounds__(256) void k_dust(DustArgs A) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= A.n) return;
+    const float rho = A.rho[c], u = A.u_rad[c], tg = A.t_gas[c];
+    const float J = u * A.c_over_4pi;
+    const float tj = sqrtf(sqrtf(A.pi_over_sigma * J));
+    const float H = A.xi4pi * kap_planck(tj) * J;
+    const float C = A.cgd_n * rho * sqrtf(tg) * (1.0f - 0.8f * __expf(-75.0f / tg));
+    // g(T) = w(T) - K with w = xi 4 sigma kappa(T) T^4 + C T increasing and convex and
+    // K = heating + C T_g.  Newton runs on ln w against ln T: for either dominant term
+    // (T^6 below 150 K, T^4 above, or T) ln w is nearly linear in ln T, so the iteration
+    // converges fast from both sides of the root.
+    const float K = H + C * tg;
+    auto wf = [&](float t, float &dw) {
+        float v, dv;
+        emis(t, v, dv);
+        dw = A.a4s * dv + C;
+        return A.a4s * v + C * t;
+    };
+    float lo = fmaxf(kFloor, fminf(tg, tj)), hi = fmaxf(kFloor, fmaxf(tg, tj));
+    int it = 0;
+    float T, dw;
+    if (hi <= kFloor) {
+        T = kFloor;
+    } else {
+        bool done = false;
+        float wl = 0.0f;
+        if (!LEARNED || lo == kFloor) {
+            wl = wf(lo, dw);
+            if (wl >= K) { T = lo; done = true; } // root at or below the lower end (floor)
+        }
+        if (!done) {
+            if (LEARNED) {
+                T = A.guess[c];
+                if (!(T > lo)) T = lo;   // also catches NaN from a poisoned network
+                if (!(T < hi)) T = hi;
+            } else {
+                // plain start: secant of the bracket in (ln T, ln w)
+                const float wh = wf(hi, dw);
+                const float ll = logf(lo), lh = logf(hi);
+                T = expf(ll + (logf(K) - logf(wl)) * (lh - ll) / (logf(wh) - logf(wl)));
+                if (!(T > lo && T < hi)) T = sqrtf(lo * hi);
+            }
+            for (it = 1; it <= A.max_iter; ++it) {
+                const float wv = wf(T, dw);
+                if (wv < K) lo = T; else hi = T;
+                float Tn = T * expf(-logf(wv / K) * wv / (T * dw));
+                if (!(Tn > lo && Tn < hi)) Tn = 0.5f * (lo + hi);
+                const bool conv = fabsf(Tn - T) <= A.tol * Tn || hi - lo <= A.tol * hi;
+                T = Tn;
+                if (conv) break;
+            }
+            if (it > A.max_iter) it = A.max_iter;
+        }
+    }
+    A.t_dust[c] = T < kFloor ? kFloor : T;
+    if (A.iters) A.iters[c] = (uint8_t)(it > 255 ? 255 : it);
+}
+
+} // namespace
+
+extern "C" int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, const float *u_rad,
+                                   const float *t_gas, const tr_dust_params *p, const tr_mlp *mlp,
+                                   float *t_dust, uint8_t *iters) {
+    if (!ctx) return TR_EINVAL;
+    if (n < 0 || (n > 0 && (!rho || !u_rad || !t_gas || !t_dust)) || !p)
+        return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad argument");
+    if (!(p->sigma > 0) || !(p->c > 0) || p->c_gd < 0 || p->xi <= 0)
+        return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad constants");
+    if (n == 0) return TR_OK;
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    DustArgs A;
+    A.n = n; A.rho = rho; A.u_rad = u_rad; A.t_gas = t_gas; A.t_dust = t_dust; A.iters = iters;
+    A.a4s = (float)(p->xi * 4.0 * p->sigma);
+    A.c_over_4pi = (float)(p->c / (4.0 * 3.14159265358979323846));
+    A.pi_over_sigma = (float)(3.14159265358979323846 / p->sigma);
+    A.xi4pi = (float)(p->xi * 4.0 * 3.14159265358979323846);
+    A.cgd_n = (float)(p->c_gd / ((1.4 * kMH) * (1.4 * kMH)));
+    A.tol = p->rel_tol > 0 ? p->rel_tol : 1e-6f;
+    A.max_iter = p->max_iter > 0 ? p->max_iter : 50;
+    const int blocks = (int)tr_div_up(n, 256);
+    A.guess = nullptr;
+    if (mlp) {
+        if (ctx->ws_guess_n < n) {
+            hipFree(ctx->ws_guess);
+            ctx->ws_guess = nullptr;
+            ctx->ws_guess_n = 0;
+            if (hipMalloc(&ctx->ws_guess, sizeof(float) * n) != hipSuccess)
+                return tr_fail(ctx, TR_ENOMEM, "guess workspace");
+            ctx->ws_guess_n = n;
+        }
+        int rc = mlp_guess(ctx, mlp, n, rho, u_rad, t_gas, ctx->ws_guess);
+        if (rc) return rc;
+        A.guess = ctx->ws_guess;
+        k_dust<true><<<blocks, 256, 0, ctx->stream>>>(A);
+    } else {
+        k_dust<false><<<blocks, 256, 0, ctx->stream>>>(A);
+    }
+    if (hipGetLastError() != hipSuccess) return tr_fail(ctx, TR_EHIP, "dust kernel launch failed");
+    return TR_OK;
+}

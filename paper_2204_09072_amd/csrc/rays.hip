@@ -1,0 +1,164 @@
+// Ray set and angular-kernel table (Sec. 4.2 of Klepitko et al. 2023).
+//
+// Rays are the HEALPix pixels (Gorski et al. 2005, NESTED numbering).  The angular
+// kernel maps a direction to its pixel through a table over discrete directions: the
+// six faces of a cube split into M x M cells, each cell holding the pixel of its centre
+// direction.  Both tables are built once per (N_side, M) on the device in FP64.
+#include "common.hpp"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ int hp_interleave(int x, int y) {
+    int r = 0;
+    for (int b = 0; b < 10; ++b) r |= ((x >> b) & 1) << (2 * b) | ((y >> b) & 1) << (2 * b + 1);
+    return r;
+}
+
+// pixel of direction (x, y, z)
+__device__ int hp_vec2pix(int ns, double x, double y, double z0) {
+    double r = sqrt(x * x + y * y + z0 * z0);
+    double z = z0 / r;
+    double phi = atan2(y, x);
+    if (phi < 0) phi += 2.0 * kPi;
+    double tt = phi / (kPi / 2.0);
+    if (tt >= 4.0) tt -= 4.0;
+    int face, fx, fy;
+    if (fabs(z) > 2.0 / 3.0) {
+        // polar cap: the cap is cut along the four meridians tt = 0, 1, 2, 3
+        int q = tt >= 3.0 ? 3 : (int)tt;
+        double tp = tt - q;
+        double w = ns * sqrt(3.0 * (1.0 - fabs(z)));
+        int a = (int)floor(tp * w), b = (int)floor((1.0 - tp) * w);
+        a = a < ns - 1 ? a : ns - 1;
+        b = b < ns - 1 ? b : ns - 1;
+        if (z > 0) {
+            face = q;
+            fx = ns - 1 - b;
+            fy = ns - 1 - a;
+        } else {
+            face = q + 8;
+            fx = a;
+            fy = b;
+        }
+    } else {
+        // equatorial belt: two families of straight pixel edges in (tt, z)
+        double up = ns * (0.5 + tt - 0.75 * z), dn = ns * (0.5 + tt + 0.75 * z);
+        int ju = (int)floor(up), jd = (int)floor(dn);
+        int fu = ju / ns, fd = jd / ns;
+        face = fu == fd ? (fu & 3) + 4 : (fu < fd ? fu : fd + 8);
+        fx = jd % ns;
+        fy = ns - 1 - ju % ns;
+    }
+    return face * ns * ns + hp_interleave(fx, fy);
+}
+
+// centre of a pixel
+__device__ void hp_pix2vec(int ns, int pix, double *v) {
+    const int row[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
+    const int col[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
+    int face = pix / (ns * ns), w = pix % (ns * ns), x = 0, y = 0;
+    for (int b = 0; b < 10; ++b) {
+        x |= ((w >> (2 * b)) & 1) << b;
+        y |= ((w >> (2 * b + 1)) & 1) << b;
+    }
+    int ring = row[face] * ns - x - y - 1;
+    int nr = ns, shift = 0;
+    double z;
+    if (ring < ns) {
+        nr = ring;
+        z = 1.0 - (double)(nr * nr) / (3.0 * ns * ns);
+    } else if (ring > 3 * ns) {
+        nr = 4 * ns - ring;
+        z = -1.0 + (double)(nr * nr) / (3.0 * ns * ns);
+    } else {
+        shift = (ring - ns) & 1;
+        z = (double)(2 * ns - ring) * 2.0 / (3.0 * ns);
+    }
+    int jp = (col[face] * nr + x - y + 1 + shift) / 2;
+    if (jp > 4 * nr) jp -= 4 * nr;
+    if (jp < 1) jp += 4 * nr;
+    double phi = ((double)jp - 0.5 * (double)(shift + 1)) * (kPi / 2.0) / (double)nr;
+    double st = sqrt((1.0 - z) * (1.0 + z));
+    v[0] = st * cos(phi);
+    v[1] = st * sin(phi);
+    v[2] = z;
+}
+
+__global__ void k_cube_table(int ns, int M, int16_t *__restrict__ tab) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 6 * (int64_t)M * M) return;
+    int f = (int)(e / ((int64_t)M * M));
+    int i = (int)((e / M) % M), j = (int)(e % M);
+    int ax = f >> 1;
+    double v[3];
+    v[ax] = (f & 1) ? -1.0 : 1.0;
+    v[ax == 0 ? 1 : 0] = (2.0 * i + 1.0) / M - 1.0;
+    v[ax == 2 ? 1 : 2] = (2.0 * j + 1.0) / M - 1.0;
+    tab[e] = (int16_t)hp_vec2pix(ns, v[0], v[1], v[2]);
+}
+
+__global__ void k_dirs(int ns, float4 *__restrict__ dirs) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= 12 * ns * ns) return;
+    double v[3];
+    hp_pix2vec(ns, p, v);
+    dirs[p] = make_float4((float)v[0], (float)v[1], (float)v[2], 0.0f);
+}
+
+} // namespace
+
+int tr_get_table(tr_ctx *ctx, int n_side, int cube_m, RayTable **out) {
+    auto key = std::make_pair(n_side, cube_m);
+    auto it = ctx->tables.find(key);
+    if (it != ctx->tables.end()) {
+        *out = &it->second;
+        return TR_OK;
+    }
+    if (n_side < 1 || n_side > 8 || (n_side & (n_side - 1)) || cube_m < 1 || cube_m > 1024)
+        return tr_fail(ctx, TR_EINVAL, "bad ray table request (n_side %d, cube_m %d)", n_side, cube_m);
+    RayTable rt;
+    rt.n_side = n_side;
+    rt.cube_m = cube_m;
+    const int64_t ne = 6 * (int64_t)cube_m * cube_m;
+    const int npix = 12 * n_side * n_side;
+    if (hipMalloc(&rt.table, sizeof(int16_t) * ne) != hipSuccess) return tr_fail(ctx, TR_ENOMEM, "table");
+    if (hipMalloc(&rt.dirs, sizeof(float4) * npix) != hipSuccess) {
+        hipFree(rt.table);
+        return tr_fail(ctx, TR_ENOMEM, "dirs");
+    }
+    k_cube_table<<<tr_div_up(ne, 256), 256, 0, ctx->stream>>>(n_side, cube_m, rt.table);
+    k_dirs<<<tr_div_up(npix, 256), 256, 0, ctx->stream>>>(n_side, rt.dirs);
+    if (hipGetLastError() != hipSuccess) {
+        hipFree(rt.table);
+        hipFree(rt.dirs);
+        return tr_fail(ctx, TR_EHIP, "table kernels failed to launch");
+    }
+    ctx->tables[key] = rt;
+    *out = &ctx->tables[key];
+    return TR_OK;
+}
+
+extern "C" int tr_ray_tables(tr_ctx *ctx, int n_side, int cube_m, int32_t *table, float *dirs) {
+    if (!ctx) return TR_EINVAL;
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    if (cube_m == 0) cube_m = 16 * n_side;
+    RayTable *rt = nullptr;
+    int rc = tr_get_table(ctx, n_side, cube_m, &rt);
+    if (rc) return rc;
+    const int64_t ne = 6 * (int64_t)cube_m * cube_m;
+    const int npix = 12 * n_side * n_side;
+    std::vector<int16_t> t16(ne);
+    std::vector<float4> d4(npix);
+    TR_HIP(ctx, hipMemcpyAsync(t16.data(), rt->table, sizeof(int16_t) * ne, hipMemcpyDeviceToHost, ctx->stream));
+    TR_HIP(ctx, hipMemcpyAsync(d4.data(), rt->dirs, sizeof(float4) * npix, hipMemcpyDeviceToHost, ctx->stream));
+    TR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t e = 0; table && e < ne; ++e) table[e] = t16[e];
+    for (int p = 0; dirs && p < npix; ++p) {
+        dirs[3 * p] = d4[p].x;
+        dirs[3 * p + 1] = d4[p].y;
+        dirs[3 * p + 2] = d4[p].z;
+    }
+    return TR_OK;
+}

@@ -1,0 +1,69 @@
+// Context lifecycle, errors and synchronisation.
+#include "common.hpp"
+
+int tr_fail(tr_ctx *ctx, int code, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+extern "C" int tr_ctx_create(tr_ctx **out, int device, void *stream) {
+    if (!out) return TR_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TR_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return TR_EHIP;
+    tr_ctx *c = new tr_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return TR_EHIP; }
+    c->n_cu = prop.multiProcessorCount;
+    if (hipMalloc(&c->d_ctl, 64 * sizeof(int)) != hipSuccess) { delete c; return TR_ENOMEM; }
+    if (hipMemset(c->d_ctl, 0, 64 * sizeof(int)) != hipSuccess) { hipFree(c->d_ctl); delete c; return TR_EHIP; }
+    if (hipHostMalloc(&c->h_err, sizeof(int)) != hipSuccess) { hipFree(c->d_ctl); delete c; return TR_ENOMEM; }
+    *out = c;
+    return TR_OK;
+}
+
+extern "C" void tr_ctx_destroy(tr_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (auto &kv : c->tables) {
+        hipFree(kv.second.table);
+        hipFree(kv.second.dirs);
+    }
+    hipFree(c->d_ctl);
+    hipFree(c->ws_guess);
+    hipHostFree(c->h_err);
+    delete c;
+}
+
+extern "C" int tr_ctx_set_stream(tr_ctx *c, void *stream) {
+    if (!c) return TR_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return TR_OK;
+}
+
+extern "C" const char *tr_last_error(const tr_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int tr_sync(tr_ctx *c) {
+    if (!c) return TR_EINVAL;
+    TR_HIP(c, hipSetDevice(c->device));
+    TR_HIP(c, hipMemcpyAsync(c->h_err, c->d_ctl + 16, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    TR_HIP(c, hipStreamSynchronize(c->stream));
+    if (*c->h_err) {
+        int e = *c->h_err;
+        TR_HIP(c, hipMemsetAsync(c->d_ctl + 16, 0, sizeof(int), c->stream));
+        TR_HIP(c, hipStreamSynchronize(c->stream));
+        return tr_fail(c, TR_EOVERFLOW, "device walk stack overflow (flag %d)", e);
+    }
+    return TR_OK;
+}
