@@ -92,7 +92,7 @@ int tr_tree_get_info(const tr_tree *tree, tr_tree_info *info);
 /* Copy the node arrays to HOST buffers (any may be NULL); synchronous.  Node order:
  * by depth, then Morton order of the node's integer coordinates; children of a node are
  * consecutive.  geo[n][4] = (centre x, y, z in u, first child or -1); meta[n] = depth |
- * child mask << 4 | leaf << 12; q[n][4] = leaf (L, A, S, 0) with the sign bit of L set
+ * child mask << 4 | leaf << 12 | (optically thick content) << 13; q[n][4] = leaf (L, A, S, 0) with the sign bit of L set
  * for optically thick leaves, h-node (L_thin, L_thick*V_thick, A_thin, A_thick);
  * vthick[n]; pcol[n][3] = mapping position in u/256; leaf_cell[n] = cell or -1.
  * Luminosities are in (length unit / u)^2 times the caller's units, areas in u^2. */

@@ -33,7 +33,8 @@ int64_t or_tree_count(const or_tree *t, int what);
 double or_tree_u_len(const or_tree *t);
 
 /* Node export in the library's documented layout (depth-major, Morton inside a depth).
- * geo [n][4] = (gx, gy, gz, first_child or -1); meta[n] = depth | mask<<4 | leaf<<12;
+ * geo [n][4] = (gx, gy, gz, first_child or -1); meta[n] = depth | mask<<4 | leaf<<12 |
+ * (thick content)<<13;
  * q [n][4]: leaf (L signed, A, S, 0), h-node (L_thin, LV_thick, A_thin, A_thick);
  * vthick[n]; pcol [n][3] (2^-8 lattice units); leaf_cell[n] (-1 for h-nodes). */
 void or_tree_export(const or_tree *t, int32_t *geo, uint32_t *meta, float *q,

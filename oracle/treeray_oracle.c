@@ -351,7 +351,9 @@ void or_tree_export(const or_tree *t, int32_t *geo, uint32_t *meta, float *q, fl
             for (int a = 0; a < 3; ++a) geo[4 * id + a] = (int32_t)t->g[3 * id + a];
             geo[4 * id + 3] = (int32_t)t->first_child[id];
         }
-        if (meta) meta[id] = (uint32_t)t->depth[id] | (uint32_t)t->mask[id] << 4 | (uint32_t)t->leaf[id] << 12;
+        if (meta)
+            meta[id] = (uint32_t)t->depth[id] | (uint32_t)t->mask[id] << 4 | (uint32_t)t->leaf[id] << 12 |
+                       (uint32_t)(t->Vk[id] > 0.0) << 13;
         if (q) {
             if (t->leaf[id]) {
                 float L = (float)t->Lb[id];

@@ -18,6 +18,9 @@ struct RayTable {
     int n_side = 0, cube_m = 0;
     int16_t *table = nullptr; // [6][M][M] pixel ids
     float4 *dirs = nullptr;   // [npix] unit vectors
+    int tile_rays = 0;        // rays per tile (consecutive NESTED pixels)
+    int n_tiles = 0;
+    float4 *caps = nullptr;   // [n_tiles] bounding cone of each tile: axis, half-angle
 };
 
 struct tr_ctx {
@@ -44,10 +47,11 @@ struct tr_tree {
     int64_t depth_off[TR_MAX_DEPTH + 2] = {0};
     // node arrays (SoA, node id order)
     int4 *geo = nullptr;       // centre (u) and first child (-1 for leaves)
-    uint32_t *meta = nullptr;  // depth | mask << 4 | leaf << 12
+    uint32_t *meta = nullptr;  // depth | mask << 4 | leaf << 12 | thick content << 13
     float4 *q = nullptr;       // node content
     float *vthick = nullptr;   // thick volume of h-nodes (u^3)
-    int4 *pcol = nullptr;      // mapping position (u / 256)
+    int4 *pcol = nullptr;      // mapping position (u / 256); .w = thick volume (float bits)
+    int4 *packed = nullptr;    // walk record: centre, depth, flags, child mask, first child
     int32_t *leaf_cell = nullptr;
     // per cell
     int32_t *node_of_cell = nullptr;

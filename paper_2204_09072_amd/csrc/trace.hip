@@ -9,22 +9,26 @@
 // extinction and an open merged segment to the next pass.
 //
 // Walk: a stack of child ranges (first child, count) in LDS; each step pops 8 ranges so
-// that the 64 lanes test 64 sibling nodes at once; the opening test and the radial
-// bin search are exact integer comparisons.
+// that the 64 lanes test 64 sibling nodes at once (one 16-byte record per node).  The
+// opening test, the pruning test and the radial bin search are exact integer
+// comparisons; the bin search takes a float estimate and falls back to 64-bit integers
+// only within rounding distance of a bin edge.  Accepted nodes that touch the pass are
+// compacted into an LDS queue and mapped 64 at a time, so the 8-point angular kernel runs
+// with every lane busy.  A block holds several such waves; they share one copy of the
+// direction-cell table in LDS when the pixel ids fit a byte.
 #include "common.hpp"
 
 namespace {
 
 constexpr float kPiF = 3.14159265358979f;
-constexpr int kStack = 640;      // ranges per wave; the walk needs at most 56 * depth + 8
-constexpr int kFields = 6;       // L_thin, A_thin, L_thick*V, A_thick, V_thick, Q
+constexpr int kStack = 640; // ranges per wave; the walk needs at most 56 * depth + 8
+constexpr int kQueue = 128; // accepted nodes waiting to be mapped (< 64 + 64)
+constexpr int kFields = 6;  // L_thin, A_thin, L_thick*V, A_thick, V_thick, Q
 
 struct TraceArgs {
-    const int4 *geo;
-    const uint32_t *meta;
-    const float4 *q;
-    const float *vthick;
-    const int4 *pcol;
+    const int4 *nodes;   // packed walk records
+    const float4 *q;     // node content
+    const int4 *pcol;    // mapping position, .w thick volume
     const int32_t *targets;
     const int32_t *leaf_cell;
     const float *cell_tau;
@@ -39,18 +43,43 @@ struct TraceArgs {
     int n_targets;
     int root_edge;
     int npix;
-    int cube_m;
+    int log2m;      // direction cells per face edge = 1 << log2m
     int n_bins;
-    int bp;      // bins per pass
+    int bp;         // bins per pass
     int n_pass;
     int chunk;
     int merge;
-    int64_t th_num2, th_den2; // opening test s^2 den^2 < num^2 d^2
+    int wide_open;  // opening test needs 64-bit products
+    int th_num2, th_den2;
     float omega;
     float j_bg;
     float c_light;
-    int lds_wave; // bytes of LDS per wave
+    int lds_wave;   // bytes of LDS per wave
+    int lds_table;  // bytes of the shared table (0: read the table from global memory)
 };
+
+struct LdsLayout {
+    int bins, flg, stk, qnode, qpk, qbeta, total;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(int npix, int bp, bool count) {
+    LdsLayout L;
+    int o = 0;
+    L.bins = o;
+    o += count ? 0 : npix * bp * kFields * 4;
+    L.flg = o;
+    o += count ? 0 : npix * 4;
+    L.stk = o;
+    o += kStack * 4;
+    L.qnode = o;
+    o += count ? 0 : kQueue * 4;
+    L.qpk = o;
+    o += count ? 0 : kQueue * 4;
+    L.qbeta = o;
+    o += count ? 0 : kQueue * 4;
+    L.total = (o + 15) & ~15;
+    return L;
+}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0): this wave's LDS traffic has landed
@@ -59,24 +88,44 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-// largest i in [0, nb] with R_i + off <= r, i.e. (FX i^2 + off)^2 <= r2 (or FX i^2 + off <= 0)
-__device__ __forceinline__ int bin_below(int64_t r2, int off, int nb) {
-    float rr = sqrtf((float)r2) - (float)off;
-    int i = rr > 0.0f ? (int)sqrtf(rr * (1.0f / TR_FX)) : 0;
-    i = i < 0 ? 0 : (i > nb ? nb : i);
-    auto ok = [&](int k) {
-        int64_t e = (int64_t)TR_FX * k * k + off;
-        return e <= 0 || e * e <= r2;
-    };
-    while (i < nb && ok(i + 1)) ++i;
-    while (i > 0 && !ok(i)) --i;
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// largest i in [0, nb] with R_i + off <= r (lattice units / 256, R_i = 256 i^2), i.e.
+// (256 i^2 + off)^2 <= r2 or 256 i^2 + off <= 0.  Float estimate, exact fallback near edges.
+__device__ __forceinline__ int bin_below(int dx, int dy, int dz, int off, int nb) {
+    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+    const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+    const float x = r - (float)off;
+    int i = x > 0.0f ? (int)sqrtf(x * (1.0f / TR_FX)) : 0;
+    i = i > nb ? nb : i;
+    const float e0 = (float)(TR_FX * i * i), e1 = (float)(TR_FX * (i + 1) * (i + 1));
+    const float tol = 4e-6f * (r + (float)(off < 0 ? -off : off) + 1.0f);
+    const bool sure = (i == 0 || x - e0 > tol) && (i == nb || e1 - x > tol);
+    if (!sure) {
+        const int64_t r2 = (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz;
+        auto ok = [&](int k) {
+            const int64_t e = (int64_t)TR_FX * k * k + off;
+            return e <= 0 || e * e <= r2;
+        };
+        i = i < 1 ? 0 : i - 1;
+        while (i < nb && ok(i + 1)) ++i;
+        while (i > 0 && !ok(i)) --i;
+    }
     return i;
 }
 
-// direction cell of an integer direction (same binning as the table: face of the largest
-// component with ties to the lower axis, then floor(M (d_a + |d_m|) / (2 |d_m|)))
-__device__ __forceinline__ int cube_cell(int dx, int dy, int dz, int M) {
-    int ax = abs(dx), ay = abs(dy), az = abs(dz);
+// exact floor(num / den) for num < 2^31, den < 2^24, quotient < 2^8, from a float reciprocal
+__device__ __forceinline__ uint32_t exact_div(uint32_t num, uint32_t den, float rc) {
+    uint32_t q = (uint32_t)((float)num * rc);
+    q -= __umul24(q, den) > num ? 1u : 0u;
+    q += __umul24(q + 1u, den) <= num ? 1u : 0u;
+    return q;
+}
+
+// direction cell of an integer direction (face of the largest component with ties to the
+// lower axis, then floor(M (d_a + |d_m|) / (2 |d_m|)) on the other two axes)
+__device__ __forceinline__ int cube_cell(int dx, int dy, int dz, int log2m) {
+    const int ax = abs(dx), ay = abs(dy), az = abs(dz);
     int f, m, ua, ub;
     if (ax >= ay && ax >= az) {
         m = ax; f = dx < 0 ? 1 : 0; ua = dy + m; ub = dz + m;
@@ -85,85 +134,107 @@ __device__ __forceinline__ int cube_cell(int dx, int dy, int dz, int M) {
     } else {
         m = az; f = dz < 0 ? 5 : 4; ua = dx + m; ub = dy + m;
     }
-    uint32_t den = 2u * (uint32_t)m;
-    uint32_t i = ((uint32_t)M * (uint32_t)ua) / den;
-    uint32_t j = ((uint32_t)M * (uint32_t)ub) / den;
-    i = i > (uint32_t)(M - 1) ? (uint32_t)(M - 1) : i;
-    j = j > (uint32_t)(M - 1) ? (uint32_t)(M - 1) : j;
-    return (f * M + (int)i) * M + (int)j;
+    const uint32_t den = 2u * (uint32_t)m;
+    const float rc = rcp((float)den);
+    const int Mm1 = (1 << log2m) - 1;
+    uint32_t i = exact_div((uint32_t)ua << log2m, den, rc);
+    uint32_t j = exact_div((uint32_t)ub << log2m, den, rc);
+    i = i > (uint32_t)Mm1 ? (uint32_t)Mm1 : i;
+    j = j > (uint32_t)Mm1 ? (uint32_t)Mm1 : j;
+    return (((f << log2m) + (int)i) << log2m) + (int)j;
 }
 
 struct Pass {
     int a, b; // radial points [a, b) held in LDS
 };
 
-// Map one accepted node (Sec. 4.2.1/4.2.2) into the pass's LDS segments.
-__device__ __forceinline__ void map_node(const TraceArgs &A, int node, bool leaf, int s, int4 c256,
-                                         Pass P, float *bins, uint32_t *flg) {
-    int4 p = A.pcol[node];
-    int dx = p.x - c256.x, dy = p.y - c256.y, dz = p.z - c256.z;
-    int64_t r2 = (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz;
-    int i = bin_below(r2, 0, A.n_bins);
-    if (i == 0) return;
-    float4 qv = A.q[node];
-    float Lt, At, LVk, Ak, Vk;
-    if (leaf) {
-        bool thick = signbit(qv.x);
-        float V = (float)s * (float)s * (float)s;
-        Lt = thick ? qv.z : qv.x + qv.z;
-        At = thick ? 0.0f : qv.y;
-        LVk = thick ? fabsf(qv.x) * V : 0.0f;
-        Ak = thick ? qv.y : 0.0f;
-        Vk = thick ? V : 0.0f;
-    } else {
-        Lt = qv.x; LVk = qv.y; At = qv.z; Ak = qv.w;
-        Vk = A.vthick[node];
-    }
-    const bool content = i >= P.a && i < P.b;
+__device__ __forceinline__ void cswap(int &a, int &b) {
+    const int lo = min(a, b), hi = max(a, b);
+    a = lo;
+    b = hi;
+}
+
+// Queue record of an accepted node: pk = content segment (i - a + 1, 0 = none) | first
+// merge flag << 6 | end of merge flags << 12 (both relative to the pass) | leaf << 18 |
+// depth << 19; beta = R_i^2 / r^2 (radial kernel).
+//
+// Map queued nodes (Sec. 4.2.1/4.2.2): one lane per node, the angular kernel from the node
+// cube's 2x2x2 sub-points, one LDS update per distinct pixel.
+template <bool LDS_TABLE>
+__device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *qnode, const uint32_t *qpk,
+                                          const float *qbeta, int4 c256, const uint8_t *tab8, float *bins,
+                                          uint32_t *flg) {
+    uint32_t starts = 0;
+    int pix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    float Lt = 0, At = 0, LVk = 0, Ak = 0, Vk = 0, beta = 0;
+    int seg = -1;
     uint32_t fbits = 0;
-    if (Vk > 0.0f && A.merge) {
-        int half = TR_FX / 2 * s;
-        int lo = bin_below(r2, half, A.n_bins);
-        lo = lo < 1 ? 1 : lo;
-        int hi = bin_below(r2, -half, A.n_bins);
-        int k0 = lo > P.a ? lo : P.a, k1 = hi < P.b ? hi : P.b;
-        for (int k = k0; k < k1; ++k) fbits |= 1u << (k - P.a);
-    }
-    if (!content && !fbits) return;
-    // radial kernel beta = R_i^2 / r^2 and the 8-point angular kernel
-    float beta = (float)((int64_t)TR_FX * TR_FX * i * i * i * i) / (float)r2;
-    int h = 64 * s;
-    int pix[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        int cx = dx + ((k & 1) ? h : -h), cy = dy + ((k & 2) ? h : -h), cz = dz + ((k & 4) ? h : -h);
-        pix[k] = A.table[cube_cell(cx, cy, cz, A.cube_m)];
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        bool first = true;
-        int cnt = 0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            bool eq = pix[j] == pix[k];
-            cnt += eq ? 1 : 0;
-            if (j < k && eq) first = false;
+    if (e >= 0) {
+        const int node = qnode[e];
+        const uint32_t pk = qpk[e];
+        beta = qbeta[e];
+        const bool leaf = (pk >> 18) & 1u;
+        const int s = A.root_edge >> ((pk >> 19) & 15u);
+        seg = (int)(pk & 63u) - 1;
+        const uint32_t k0 = (pk >> 6) & 63u, k1 = (pk >> 12) & 63u;
+        if (k1 > k0) fbits = (k1 >= 32u ? 0xffffffffu : ((1u << k1) - 1u)) & ~((1u << k0) - 1u);
+        const float4 qv = A.q[node];
+        const int4 p = A.pcol[node];
+        if (leaf) {
+            const bool thick = signbit(qv.x);
+            const float V = (float)s * (float)s * (float)s;
+            Lt = thick ? qv.z : qv.x + qv.z;
+            At = thick ? 0.0f : qv.y;
+            LVk = thick ? fabsf(qv.x) * V : 0.0f;
+            Ak = thick ? qv.y : 0.0f;
+            Vk = thick ? V : 0.0f;
+        } else {
+            Lt = qv.x; LVk = qv.y; At = qv.z; Ak = qv.w;
+            Vk = __int_as_float(p.w);
         }
-        if (!first) continue;
-        float al = 0.125f * (float)cnt;
-        if (content) {
-            float *bb = bins + ((size_t)pix[k] * A.bp + (i - P.a)) * kFields;
-            float ab = al * beta;
-            if (Lt != 0.0f) atomicAdd(bb + 0, ab * Lt);
-            if (At != 0.0f) atomicAdd(bb + 1, ab * At);
-            if (Vk > 0.0f) {
-                atomicAdd(bb + 2, al * LVk);
-                atomicAdd(bb + 3, al * Ak);
-                atomicAdd(bb + 4, al * Vk);
-                atomicAdd(bb + 5, ab * Vk);
+        const int dx = p.x - c256.x, dy = p.y - c256.y, dz = p.z - c256.z;
+        const int h = 64 * s;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int cx = dx + ((k & 1) ? h : -h), cy = dy + ((k & 2) ? h : -h), cz = dz + ((k & 4) ? h : -h);
+            const int cell = cube_cell(cx, cy, cz, A.log2m);
+            pix[k] = LDS_TABLE ? (int)tab8[cell] : (int)A.table[cell];
+        }
+        // sort the 8 pixel ids (19-comparator network), then mark runs of equal ids
+        cswap(pix[0], pix[2]); cswap(pix[1], pix[3]); cswap(pix[4], pix[6]); cswap(pix[5], pix[7]);
+        cswap(pix[0], pix[4]); cswap(pix[1], pix[5]); cswap(pix[2], pix[6]); cswap(pix[3], pix[7]);
+        cswap(pix[0], pix[1]); cswap(pix[2], pix[3]); cswap(pix[4], pix[5]); cswap(pix[6], pix[7]);
+        cswap(pix[2], pix[4]); cswap(pix[3], pix[5]);
+        cswap(pix[1], pix[4]); cswap(pix[3], pix[6]);
+        cswap(pix[1], pix[2]); cswap(pix[3], pix[4]); cswap(pix[5], pix[6]);
+        starts = 1u;
+#pragma unroll
+        for (int k = 1; k < 8; ++k) starts |= (pix[k] != pix[k - 1] ? 1u : 0u) << k;
+    }
+    // one LDS update per distinct pixel; the loop runs as often as the busiest lane needs
+    while (__ballot(starts != 0u)) {
+        if (starts) {
+            const int k = __builtin_ctz(starts);
+            starts &= starts - 1u;
+            const int kn = starts ? __builtin_ctz(starts) : 8;
+            int px = pix[0];
+#pragma unroll
+            for (int j = 1; j < 8; ++j) px = k == j ? pix[j] : px;
+            const float al = 0.125f * (float)(kn - k);
+            if (seg >= 0) {
+                float *bb = bins + (px * A.bp + seg) * kFields;
+                const float ab = al * beta;
+                if (Lt != 0.0f) atomicAdd(bb + 0, ab * Lt);
+                if (At != 0.0f) atomicAdd(bb + 1, ab * At);
+                if (Vk > 0.0f) {
+                    atomicAdd(bb + 2, al * LVk);
+                    atomicAdd(bb + 3, al * Ak);
+                    atomicAdd(bb + 4, al * Vk);
+                    atomicAdd(bb + 5, ab * Vk);
+                }
             }
+            if (fbits) atomicOr(flg + px, fbits);
         }
-        if (fbits) atomicOr(flg + pix[k], fbits);
     }
 }
 
@@ -176,35 +247,45 @@ struct RayState {
     float acc[NSLOT][kFields];
 };
 
-// One closed segment at R_i (Sec. 4.3.1, 4.3.2): returns nothing, updates the ray.
+// One closed segment at R_i (Sec. 4.3.1, 4.3.2): updates the ray's flux and extinction.
 __device__ __forceinline__ void integrate_segment(const float *s, int i, float omega, float &tau_thin,
                                                   float &eps_thick, float &Fh) {
-    float R2 = (float)i * (float)i * (float)i * (float)i;
-    float tt = s[1] / (omega * R2);
+    const float R2 = (float)i * (float)i * (float)i * (float)i;
+    const float rR2 = rcp(R2);
+    const float tt = s[1] * rcp(omega) * rR2;
     float omt = 0.0f, tk = 0.0f, Fk = 0.0f;
     if (s[4] > 0.0f) {
-        float cb = cbrtf(s[4]);
-        omt = (s[5] / s[4]) * (cb * cb) / R2;
+        const float cb = cbrtf(s[4]);
+        const float rv = rcp(s[4]);
+        omt = s[5] * rv * (cb * cb) * rR2;
         omt = omt > omega ? omega : omt;
-        if (omt > 0.0f) tk = s[3] / (omt * R2);
-        Fk = omt * s[2] / s[4];
+        if (omt > 0.0f) tk = s[3] * rcp(omt) * rR2;
+        Fk = omt * s[2] * rv;
     }
-    float f = omt / omega;
-    float phi = tt > 0.0f ? -expm1f(-tt) / tt : 1.0f;
-    float Ft = phi * s[0] / (4.0f * kPiF * R2);
-    float den = s[1] + f * s[3];
-    float Fs = den > 0.0f ? (Ft * s[1] + Fk * f * s[3]) / den : Ft;
+    const float f = omt * rcp(omega);
+    const float phi = tt > 0.0f ? -expm1f(-tt) * rcp(tt) : 1.0f;
+    const float Ft = phi * s[0] * rR2 * (0.25f / kPiF);
+    const float den = s[1] + f * s[3];
+    const float Fs = den > 0.0f ? (Ft * s[1] + Fk * f * s[3]) * rcp(den) : Ft;
     Fh += __expf(-tau_thin) * eps_thick * Fs;
     tau_thin += tt;
     eps_thick *= (1.0f - f) + f * __expf(-tk);
 }
 
-template <int NSLOT, bool COUNT>
-__device__ void trace_target(const TraceArgs &A, int ti, float *bins, uint32_t *flg, int2 *stk) {
+template <int NSLOT, bool COUNT, bool LDS_TABLE>
+__device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_t *tab8) {
+    const LdsLayout LL = lds_layout(A.npix, A.bp, COUNT);
+    float *bins = reinterpret_cast<float *>(lds + LL.bins);
+    uint32_t *flg = reinterpret_cast<uint32_t *>(lds + LL.flg);
+    uint32_t *stk = reinterpret_cast<uint32_t *>(lds + LL.stk);
+    int *qnode = reinterpret_cast<int *>(lds + LL.qnode);
+    uint32_t *qpk = reinterpret_cast<uint32_t *>(lds + LL.qpk);
+    float *qbeta = reinterpret_cast<float *>(lds + LL.qbeta);
     const int lane = lane_id();
     const int tid = A.targets[ti];
-    const int4 tg = A.geo[tid];
-    const int4 c256 = make_int4(tg.x * TR_FX, tg.y * TR_FX, tg.z * TR_FX, 0);
+    const int4 tr = A.nodes[tid];
+    const int tx = tr.x & 0xffff, ty = tr.y & 0xffff, tz = tr.z;
+    const int4 c256 = make_int4(tx * TR_FX, ty * TR_FX, tz * TR_FX, 0);
     RayState<NSLOT> R;
 #pragma unroll
     for (int k = 0; k < NSLOT; ++k) {
@@ -222,75 +303,161 @@ __device__ void trace_target(const TraceArgs &A, int ti, float *bins, uint32_t *
         P.a = 1 + ps * A.bp;
         P.b = P.a + A.bp;
         if (P.b > A.n_bins + 1) P.b = A.n_bins + 1;
+        const int lo_cut = P.a * P.a, hi_cut = P.b * P.b;
+        const int a4 = lo_cut * lo_cut, b4 = hi_cut * hi_cut; // R_a^2, R_b^2 in lattice units
+        const bool last = P.b > A.n_bins;
         if (!COUNT) {
             const int nf = A.npix * A.bp * kFields;
             for (int k = lane; k < nf; k += 64) bins[k] = 0.0f;
             for (int k = lane; k < A.npix; k += 64) flg[k] = 0u;
         }
-        // squared pruning radii (lattice units): keep a subtree when
-        // r_max + s/4 >= R_a and r_min - s/4 < R_b
-        if (lane == 0) stk[0] = make_int2(0, 1);
-        int sp = 1;
+        if (lane == 0) stk[0] = 0u; // the root: first node 0, one node
+        int sp = 1, qn = 0;
         wave_sync();
-        while (sp > 0) {
-            const int npop = sp < 8 ? sp : 8;
-            const int r = lane >> 3, k = lane & 7;
-            int2 rg = r < npop ? stk[sp - 1 - r] : make_int2(0, 0);
-            sp -= npop;
-            wave_sync();
-            int node = (r < npop && k < rg.y) ? rg.x + k : -1;
-            bool open = false;
-            int2 push = make_int2(0, 0);
-            if (node >= 0) {
-                const int4 g = A.geo[node];
-                const uint32_t mt = A.meta[node];
-                const int s = A.root_edge >> (mt & 15u);
-                const bool leaf = (mt >> 12) & 1u;
-                if (leaf) {
-                    if (node != tid) {
-                        ++n_b;
-                        if (!COUNT) map_node(A, node, true, s, c256, P, bins, flg);
-                    }
-                } else {
-                    const int64_t ddx = g.x - tg.x, ddy = g.y - tg.y, ddz = g.z - tg.z;
-                    const int64_t d2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                    if ((int64_t)s * s * A.th_den2 < A.th_num2 * d2) {
-                        ++n_h;
-                        if (!COUNT) map_node(A, node, false, s, c256, P, bins, flg);
-                    } else {
-                        ++n_open;
-                        bool keep = true;
-                        if (!COUNT) {
-                            const int hs = s / 2, q4 = s / 4;
-                            const int ax = abs((int)ddx), ay = abs((int)ddy), az = abs((int)ddz);
-                            const int64_t nx = ax > hs ? ax - hs : 0, ny = ay > hs ? ay - hs : 0,
-                                          nz = az > hs ? az - hs : 0;
-                            const int64_t fx = ax + hs, fy = ay + hs, fz = az + hs;
-                            const int64_t rmin2 = nx * nx + ny * ny + nz * nz;
-                            const int64_t rmax2 = fx * fx + fy * fy + fz * fz;
-                            const int64_t lo = (int64_t)P.a * P.a - q4;
-                            const int64_t hi = (int64_t)P.b * P.b + q4;
-                            if (lo > 0 && rmax2 < lo * lo) keep = false;
-                            if (P.b <= A.n_bins && rmin2 >= hi * hi) keep = false;
+        while (sp > 0 || qn > 0) {
+            if (sp > 0) {
+                const int npop = sp < 8 ? sp : 8;
+                const int r = lane >> 3, k = lane & 7;
+                const uint32_t rg = r < npop ? stk[sp - 1 - r] : 0u;
+                sp -= npop;
+                wave_sync();
+                const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
+                bool open = false, enq = false;
+                uint32_t push = 0, pk = 0;
+                float beta = 0.0f;
+                if (node >= 0) {
+                    const int4 nd = A.nodes[node];
+                    const int depth = (nd.x >> 16) & 15;
+                    const bool leaf = (nd.x >> 20) & 1;
+                    const bool thick = (nd.x >> 21) & 1;
+                    const int s = A.root_edge >> depth;
+                    const int vx = (nd.x & 0xffff) - tx, vy = (nd.y & 0xffff) - ty, vz = nd.z - tz;
+                    bool acc = false;
+                    if (leaf) {
+                        if (node != tid) {
+                            ++n_b;
+                            acc = true;
                         }
-                        if (keep) {
-                            open = true;
-                            push = make_int2(g.w, __builtin_popcount((mt >> 4) & 255u));
+                    } else {
+                        // |v| < 2^12, s < 2^12: d2 and s^2 fit 24 bits
+                        const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
+                        const int s2 = __mul24(s, s);
+                        const bool accept = A.wide_open ? (int64_t)s2 * A.th_den2 < (int64_t)A.th_num2 * d2
+                                                        : s2 * A.th_den2 < A.th_num2 * d2;
+                        if (accept) {
+                            ++n_h;
+                            acc = true;
+                        } else {
+                            ++n_open;
+                            bool keep = true;
+                            if (!COUNT) {
+                                // keep a subtree when r_max + s/4 >= R_a and r_min - s/4 < R_b
+                                const int hs = s >> 1, q4 = s >> 2;
+                                const int ax = abs(vx), ay = abs(vy), az = abs(vz);
+                                const int nx = max(ax - hs, 0), ny = max(ay - hs, 0), nz = max(az - hs, 0);
+                                const int fx = ax + hs, fy = ay + hs, fz = az + hs;
+                                const int rmin2 = __mul24(nx, nx) + __mul24(ny, ny) + __mul24(nz, nz);
+                                const int rmax2 = __mul24(fx, fx) + __mul24(fy, fy) + __mul24(fz, fz);
+                                const int lo = lo_cut - q4, hi = hi_cut + q4;
+                                if (lo > 0 && rmax2 < __mul24(lo, lo)) keep = false;
+                                if (!last && rmin2 >= __mul24(hi, hi)) keep = false;
+                            }
+                            if (keep) {
+                                open = true;
+                                push = ((uint32_t)nd.w << 3) |
+                                       (uint32_t)(__builtin_popcount((nd.y >> 16) & 255) - 1);
+                            }
+                        }
+                    }
+                    if (!COUNT && acc) {
+                        // exact integer pre-test in lattice units: the mapping position lies in
+                        // the node cube, so r is within [r_min, r_max]; thick material reaches a
+                        // further s/2 for the merge flags.  R_i = i^2, so R_i <= r <=> i^4 <= r^2.
+                        const int ext = thick && A.merge ? (s >> 1) : 0;
+                        bool maybe;
+                        if (leaf) {
+                            const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
+                            if (ext == 0) {
+                                maybe = d2 >= a4 && (last || d2 < b4);
+                            } else {
+                                const int lo = P.a * P.a - ext, hi = P.b * P.b + ext;
+                                maybe = (lo <= 0 || d2 >= __mul24(lo, lo)) && (last || d2 < __mul24(hi, hi));
+                            }
+                        } else {
+                            const int hs = (s >> 1) + ext;
+                            const int ax = abs(vx), ay = abs(vy), az = abs(vz);
+                            const int nx = max(ax - hs, 0), ny = max(ay - hs, 0), nz = max(az - hs, 0);
+                            const int fx = ax + hs, fy = ay + hs, fz = az + hs;
+                            const int rmin2 = __mul24(nx, nx) + __mul24(ny, ny) + __mul24(nz, nz);
+                            const int rmax2 = __mul24(fx, fx) + __mul24(fy, fy) + __mul24(fz, fz);
+                            maybe = rmax2 >= a4 && (last || rmin2 < b4);
+                        }
+                        if (maybe) {
+                            int dx, dy, dz;
+                            if (leaf) {
+                                dx = vx * TR_FX; dy = vy * TR_FX; dz = vz * TR_FX;
+                            } else {
+                                const int4 p = A.pcol[node];
+                                dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
+                            }
+                            const int i = bin_below(dx, dy, dz, 0, A.n_bins);
+                            if (i > 0) {
+                                const bool content = i >= P.a && i < P.b;
+                                int k0 = 0, k1 = 0;
+                                if (ext) {
+                                    const int half = TR_FX / 2 * s;
+                                    int lo = bin_below(dx, dy, dz, half, A.n_bins);
+                                    lo = lo < 1 ? 1 : lo;
+                                    const int hi = bin_below(dx, dy, dz, -half, A.n_bins);
+                                    k0 = lo > P.a ? lo : P.a;
+                                    k1 = hi < P.b ? hi : P.b;
+                                    if (k1 <= k0) { k0 = 0; k1 = 0; } else { k0 -= P.a; k1 -= P.a; }
+                                }
+                                if (content || k1 > k0) {
+                                    enq = true;
+                                    pk = (content ? (uint32_t)(i - P.a + 1) : 0u) | ((uint32_t)k0 << 6) |
+                                         ((uint32_t)k1 << 12) | ((leaf ? 1u : 0u) << 18) |
+                                         ((uint32_t)depth << 19);
+                                    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+                                    const float R2 = (float)(TR_FX * i * i);
+                                    beta = (R2 * R2) * rcp(fx * fx + fy * fy + fz * fz);
+                                }
+                            }
                         }
                     }
                 }
+                const uint64_t below = (1ull << lane) - 1ull;
+                const uint64_t bal = __ballot(open);
+                const int pos = __builtin_popcountll(bal & below);
+                const int npush = __builtin_popcountll(bal);
+                if (open && sp + pos < kStack) stk[sp + pos] = push;
+                if (sp + npush > kStack) {
+                    if (lane == 0) atomicOr(A.err, 4);
+                    sp = kStack;
+                } else {
+                    sp += npush;
+                }
+                if (!COUNT) {
+                    const uint64_t qb = __ballot(enq);
+                    if (enq) {
+                        const int qp = qn + __builtin_popcountll(qb & below);
+                        qnode[qp] = node;
+                        qpk[qp] = pk;
+                        qbeta[qp] = beta;
+                    }
+                    qn += __builtin_popcountll(qb);
+                }
+                wave_sync();
             }
-            const uint64_t bal = __ballot(open);
-            const int pos = __builtin_popcountll(bal & ((1ull << lane) - 1ull));
-            const int npush = __builtin_popcountll(bal);
-            if (open && sp + pos < kStack) stk[sp + pos] = push;
-            if (sp + npush > kStack) {
-                if (lane == 0) atomicOr(A.err, 4);
-                sp = kStack;
-            } else {
-                sp += npush;
+            if (COUNT) continue;
+            // map a full batch, or whatever is left once the walk of the pass is done
+            if (qn >= 64 || (sp == 0 && qn > 0)) {
+                const int nq = qn >= 64 ? 64 : qn;
+                const int e = lane < nq ? qn - nq + lane : -1;
+                map_queue<LDS_TABLE>(A, e, qnode, qpk, qbeta, c256, tab8, bins, flg);
+                qn -= nq;
+                wave_sync();
             }
-            wave_sync();
         }
         if (COUNT) break;
         // integrate the pass's segments outwards, one lane per ray
@@ -300,14 +467,14 @@ __device__ void trace_target(const TraceArgs &A, int ti, float *bins, uint32_t *
             if (h >= A.npix) continue;
             const uint32_t fl = flg[h];
             for (int i = P.a; i < P.b; ++i) {
-                const float *v = bins + ((size_t)h * A.bp + (i - P.a)) * kFields;
+                const float *v = bins + (h * A.bp + (i - P.a)) * kFields;
                 if (R.run_i[sl] == 0) {
                     R.run_i[sl] = i;
 #pragma unroll
                     for (int f = 0; f < kFields; ++f) R.acc[sl][f] = v[f];
                 } else {
                     // inverse-square content moves to the merged segment's R_i
-                    const float T = (float)R.run_i[sl] / (float)i;
+                    const float T = (float)R.run_i[sl] * rcp((float)i);
                     const float T4 = (T * T) * (T * T);
                     R.acc[sl][0] += T4 * v[0];
                     R.acc[sl][1] += T4 * v[1];
@@ -328,7 +495,6 @@ __device__ void trace_target(const TraceArgs &A, int ti, float *bins, uint32_t *
     }
     const int cell = A.leaf_cell[tid];
     if (COUNT) {
-        // reduce the per-lane counters
         for (int o = 32; o > 0; o >>= 1) {
             n_b += __shfl_xor(n_b, o);
             n_h += __shfl_xor(n_h, o);
@@ -362,9 +528,9 @@ __device__ void trace_target(const TraceArgs &A, int ti, float *bins, uint32_t *
     }
     if (lane == 0) {
         const float src = A.cell_src[cell];
-        float Jv = js / (4.0f * kPiF);
+        float Jv = js * (0.25f / kPiF);
         if (src > 0.0f) {
-            const float e = (float)(A.root_edge >> (A.meta[tid] & 15u));
+            const float e = (float)(A.root_edge >> ((tr.x >> 16) & 15));
             Jv += -expm1f(-0.5f * A.cell_tau[cell]) * src / (4.0f * kPiF * (e * e));
         }
         A.J[cell] = Jv;
@@ -375,19 +541,35 @@ __device__ void trace_target(const TraceArgs &A, int ti, float *bins, uint32_t *
     }
 }
 
-template <int NSLOT, bool COUNT>
-__global__ __launch_bounds__(64) void k_trace(TraceArgs A) {
+template <int NSLOT, bool COUNT, bool LDS_TABLE>
+__global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
     extern __shared__ __align__(16) char smem[];
-    float *bins = reinterpret_cast<float *>(smem);
-    uint32_t *flg = reinterpret_cast<uint32_t *>(bins + (COUNT ? 0 : A.npix * A.bp * kFields));
-    int2 *stk = reinterpret_cast<int2 *>(smem + (COUNT ? 0 : A.lds_wave - kStack * sizeof(int2)));
-    for (;;) {
-        int t0 = 0;
-        if (lane_id() == 0) t0 = atomicAdd(A.work, A.chunk);
-        t0 = __shfl(t0, 0);
-        if (t0 >= A.n_targets) break;
-        const int t1 = t0 + A.chunk < A.n_targets ? t0 + A.chunk : A.n_targets;
-        for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT>(A, ti, bins, flg, stk);
+    const uint8_t *tab8 = reinterpret_cast<const uint8_t *>(smem);
+    if (LDS_TABLE) {
+        uint8_t *t = reinterpret_cast<uint8_t *>(smem);
+        const int ne = 6 << (2 * A.log2m);
+        for (int k = threadIdx.x; k < ne; k += blockDim.x) t[k] = (uint8_t)A.table[k];
+        __syncthreads();
+    }
+    char *lds = smem + A.lds_table + (threadIdx.x >> 6) * A.lds_wave;
+    // XCD-aware work distribution: blocks are dispatched round-robin over the 8 XCDs, so
+    // block b runs on XCD b % 8; each XCD takes targets from its own contiguous range of
+    // the (Morton-ordered) target list and keeps that region of the tree in its L2.  A
+    // wave whose range is exhausted helps the next XCD's range.
+    const int home = blockIdx.x & 7;
+    const int per = (A.n_targets + 7) >> 3;
+    for (int x = 0; x < 8; ++x) {
+        const int r = (home + x) & 7;
+        const int lo = r * per;
+        const int hi = min(lo + per, A.n_targets);
+        for (;;) {
+            int t0 = 0;
+            if (lane_id() == 0) t0 = atomicAdd(A.work + r, A.chunk);
+            t0 = __shfl(t0, 0) + lo;
+            if (t0 >= hi) break;
+            const int t1 = t0 + A.chunk < hi ? t0 + A.chunk : hi;
+            for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE>(A, ti, lds, tab8);
+        }
     }
 }
 
@@ -430,9 +612,16 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
         return tr_fail(ctx, TR_EINVAL, "n_side must be 1, 2, 4 or 8 (got %d)", ns);
     int64_t num = p->theta_num, den = p->theta_den;
     if (num == 0 && den == 0) { num = 1; den = 2 * ns; }
-    if (num < 0 || den <= 0) return tr_fail(ctx, TR_EINVAL, "bad opening angle %lld/%lld", (long long)num, (long long)den);
+    if (num < 0 || den <= 0 || num > 1024 || den > 1024)
+        return tr_fail(ctx, TR_EINVAL, "bad opening angle %lld/%lld", (long long)num, (long long)den);
     const int M = p->cube_m ? p->cube_m : 16 * ns;
-    if (M < 1 || M > 256) return tr_fail(ctx, TR_EINVAL, "cube_m must be in [1, 256]");
+    if (M < 2 || M > 256 || (M & (M - 1)))
+        return tr_fail(ctx, TR_EINVAL, "cube_m must be a power of two in [2, 256]");
+    int log2m = 0;
+    while ((1 << log2m) < M) ++log2m;
+    if (t->n_bins > 63) return tr_fail(ctx, TR_EINVAL, "too many ray segments (%d)", t->n_bins);
+    if (t->n_node >= ((int64_t)1 << 29)) return tr_fail(ctx, TR_EINVAL, "too many nodes for the walk stack");
+    if (t->root_edge > 2048) return tr_fail(ctx, TR_EINVAL, "grid too fine for the walk's integer ranges");
     TR_HIP(ctx, hipSetDevice(ctx->device));
     RayTable *rt = nullptr;
     int rc = tr_get_table(ctx, ns, M, &rt);
@@ -440,47 +629,52 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     const int npix = 12 * ns * ns;
     int bp = p->bins_per_pass;
     if (bp <= 0) {
-        // largest pass that keeps at least 4 waves per CU within 160 KB of LDS
+        // the largest pass with per-wave LDS under 20 KB (several waves per CU)
         bp = t->n_bins;
-        while (bp > 1 && (size_t)npix * bp * kFields * 4 + npix * 4 + kStack * 8 > 40 * 1024) --bp;
+        while (bp > 1 && lds_layout(npix, bp, false).total > 20 * 1024) --bp;
     }
     if (bp > t->n_bins) bp = t->n_bins;
-    if (bp > 32) bp = 32;
+    if (bp > 31) bp = 31;
     if (bp < 1) bp = 1;
     TraceArgs A;
-    A.geo = t->geo; A.meta = t->meta; A.q = t->q; A.vthick = t->vthick; A.pcol = t->pcol;
+    A.nodes = t->packed; A.q = t->q; A.pcol = t->pcol;
     A.targets = t->targets; A.leaf_cell = t->leaf_cell; A.cell_tau = t->cell_tau; A.cell_src = t->cell_src;
     A.table = rt->table; A.dirs = rt->dirs;
     A.work = ctx->d_ctl; A.err = ctx->d_ctl + 16;
     A.J = J; A.F = F; A.u_rad = u_rad; A.counters = counters;
     A.n_cells = t->n_cells; A.n_targets = (int)t->n_cells; A.root_edge = (int)t->root_edge;
-    A.npix = npix; A.cube_m = M; A.n_bins = t->n_bins; A.bp = bp;
+    A.npix = npix; A.log2m = log2m; A.n_bins = t->n_bins; A.bp = bp;
     A.n_pass = (int)tr_div_up(t->n_bins, bp);
     A.chunk = p->chunk > 0 ? p->chunk : 4;
     A.merge = p->merge ? 1 : 0;
-    A.th_num2 = num * num; A.th_den2 = den * den;
+    A.th_num2 = (int)(num * num); A.th_den2 = (int)(den * den);
+    // 32-bit products are exact when num^2 d^2 and den^2 s^2 stay below 2^31
+    const int64_t max_d2 = 3 * t->root_edge * t->root_edge, max_s2 = t->root_edge * t->root_edge;
+    A.wide_open = (num * num * max_d2 >= ((int64_t)1 << 31) || den * den * max_s2 >= ((int64_t)1 << 31)) ? 1 : 0;
     A.omega = (float)(4.0 * 3.14159265358979323846 / npix);
     A.j_bg = p->j_bg;
     A.c_light = (float)t->c_light;
-    A.lds_wave = count ? (int)(kStack * sizeof(int2))
-                       : (int)((size_t)npix * bp * kFields * 4 + (size_t)npix * 4 + kStack * sizeof(int2));
-    A.lds_wave = (A.lds_wave + 15) & ~15;
-    int per_cu = p->blocks_per_cu > 0 ? p->blocks_per_cu : (int)((160 * 1024) / A.lds_wave);
-    if (per_cu > 16) per_cu = 16;
-    if (per_cu < 1) per_cu = 1;
-    const int grid = ctx->n_cu * per_cu;
-    k_zero_int<<<1, 64, 0, ctx->stream>>>(ctx->d_ctl, 1);
-    const size_t lds = (size_t)A.lds_wave;
-#define LAUNCH(NS_, C_)                                                                     \
-    hipLaunchKernelGGL((k_trace<NS_, C_>), dim3(grid), dim3(64), lds, ctx->stream, A)
+    A.lds_wave = lds_layout(npix, bp, count).total;
+    const bool tab_lds = !count && npix <= 256;
+    A.lds_table = tab_lds ? ((6 * M * M + 15) & ~15) : 0;
+    // waves per block: as many as fit in 160 KB together with the shared table
+    int per_block = p->blocks_per_cu > 0 ? p->blocks_per_cu : (160 * 1024 - A.lds_table) / A.lds_wave;
+    if (per_block > (npix > 192 ? 4 : 16)) per_block = npix > 192 ? 4 : 16;
+    if (per_block < 1) per_block = 1;
+    const size_t lds = (size_t)A.lds_table + (size_t)per_block * A.lds_wave;
+    if (lds > 160 * 1024) return tr_fail(ctx, TR_EINVAL, "LDS per block too large (%zu bytes)", lds);
+    const int grid = ctx->n_cu;
+    k_zero_int<<<1, 64, 0, ctx->stream>>>(ctx->d_ctl, 8);
+    const dim3 blk(64 * per_block);
+#define LAUNCH(NS_, C_, T_) hipLaunchKernelGGL((k_trace<NS_, C_, T_>), dim3(grid), blk, lds, ctx->stream, A)
     if (count) {
-        LAUNCH(1, true);
+        LAUNCH(1, true, false);
     } else if (npix <= 64) {
-        LAUNCH(1, false);
+        LAUNCH(1, false, true);
     } else if (npix <= 192) {
-        LAUNCH(3, false);
+        LAUNCH(3, false, true);
     } else {
-        LAUNCH(12, false);
+        LAUNCH(12, false, false);
     }
 #undef LAUNCH
     if (hipGetLastError() != hipSuccess) return tr_fail(ctx, TR_EHIP, "trace kernel launch failed");

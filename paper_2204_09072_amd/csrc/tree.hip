@@ -152,7 +152,7 @@ struct Scratch64 {
 __global__ void k_leaf_fill(int64_t n_cells, const float *__restrict__ rho,
                             const float *__restrict__ kappa, const float *__restrict__ t_dust,
                             const double *__restrict__ src, const int32_t *__restrict__ node_of_cell,
-                            const uint32_t *__restrict__ meta, int64_t root_edge, double u_len,
+                            uint32_t *__restrict__ meta, int64_t root_edge, double u_len,
                             double sigma, Scratch64 S64, float4 *__restrict__ q,
                             float *__restrict__ vthick, float *__restrict__ cell_tau,
                             float *__restrict__ cell_kappa, float *__restrict__ cell_src) {
@@ -189,6 +189,7 @@ __global__ void k_leaf_fill(int64_t n_cells, const float *__restrict__ rho,
         S64.Vk[id] = V;
         S64.xi[id] = La * (e * e) + Sv;
         o.x = copysignf((float)La, -1.0f);
+        meta[id] |= 1u << 13; // thick content
     }
     o.y = (float)A;
     o.z = (float)Sv;
@@ -203,7 +204,7 @@ __global__ void k_leaf_fill(int64_t n_cells, const float *__restrict__ rho,
 // h-nodes of one depth (App. A): thin and thick content summed separately, star light in
 // the thin luminosity, centre of luminosity from the sub-nodes' own mapping positions.
 __global__ void k_up(int64_t lo, int64_t hi, const int4 *__restrict__ geo,
-                     const uint32_t *__restrict__ meta, Scratch64 S64, float4 *__restrict__ q,
+                     uint32_t *__restrict__ meta, Scratch64 S64, float4 *__restrict__ q,
                      float *__restrict__ vthick, int4 *__restrict__ pcol) {
     int64_t id = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= hi) return;
@@ -241,9 +242,23 @@ __global__ void k_up(int64_t lo, int64_t hi, const int4 *__restrict__ geo,
         p.y = (int)(g256[1] + (int64_t)rint(n1 / X));
         p.z = (int)(g256[2] + (int64_t)rint(n2 / X));
     }
+    p.w = __float_as_int((float)Vk); // the walk reads the thick volume with the position
     pcol[id] = p;
     q[id] = make_float4((float)Lt, (float)LVk, (float)At, (float)Ak);
     vthick[id] = (float)Vk;
+    if (Vk > 0.0) meta[id] = mt | (1u << 13); // thick content
+}
+
+// Walk record of every node, one 16-byte load per visit:
+// (gx | depth << 16 | leaf << 20 | thick << 21, gy | child mask << 16, gz, first child)
+__global__ void k_pack(int64_t n, const int4 *__restrict__ geo, const uint32_t *__restrict__ meta,
+                       int4 *__restrict__ packed) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int4 g = geo[id];
+    const uint32_t m = meta[id];
+    packed[id] = make_int4(g.x | (int)((m & 15u) << 16) | (int)(((m >> 12) & 3u) << 20),
+                           g.y | (int)(((m >> 4) & 255u) << 16), g.z, g.w);
 }
 
 template <class T>
@@ -259,6 +274,7 @@ int dev_alloc(tr_ctx *ctx, T **p, int64_t n) {
 extern "C" void tr_tree_free(tr_tree *t) {
     if (!t) return;
     hipFree(t->geo); hipFree(t->meta); hipFree(t->q); hipFree(t->vthick); hipFree(t->pcol);
+    hipFree(t->packed);
     hipFree(t->leaf_cell); hipFree(t->node_of_cell); hipFree(t->targets);
     hipFree(t->cell_tau); hipFree(t->cell_kappa); hipFree(t->cell_src);
     delete t;
@@ -392,6 +408,7 @@ extern "C" int tr_build_tree(tr_ctx *ctx, const tr_grid *grid, const float *rho,
     TRY(dev_alloc(ctx, &t->q, n));
     TRY(dev_alloc(ctx, &t->vthick, n));
     TRY(dev_alloc(ctx, &t->pcol, n));
+    TRY(dev_alloc(ctx, &t->packed, n));
     TRY(dev_alloc(ctx, &t->leaf_cell, n));
     TRY(dev_alloc(ctx, &t->node_of_cell, nc));
     TRY(dev_alloc(ctx, &t->targets, nc));
@@ -430,6 +447,7 @@ extern "C" int tr_build_tree(tr_ctx *ctx, const tr_grid *grid, const float *rho,
         if (hi > lo)
             k_up<<<tr_div_up(hi - lo, TPB), TPB, 0, st>>>(lo, hi, t->geo, t->meta, S64, t->q, t->vthick, t->pcol);
     }
+    k_pack<<<tr_div_up(n, TPB), TPB, 0, st>>>(n, t->geo, t->meta, t->packed);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
         cleanup(); return tr_fail(ctx, TR_EHIP, "tree kernels failed");
     }
