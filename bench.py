@@ -133,7 +133,7 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--bins-per-pass", type=int, default=0)
-    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -160,7 +160,7 @@ def main():
                       "loss": [round(l, 6) for _, l in losses]}
         log("guess network trained", train_info)
 
-    p = params_of(w, bins_per_pass=args.bins_per_pass, blocks_per_cu=args.blocks_per_cu,
+    p = params_of(w, bins_per_pass=args.bins_per_pass, waves_per_block=args.waves_per_block,
                   chunk=args.chunk)
     n = w.n_cells
     J = torch.empty(n, device="cuda")

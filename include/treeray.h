@@ -108,9 +108,10 @@ typedef struct tr_trace_params {
                               0 selects 16 N_side */
     int32_t merge;         /* 1: merge segments spanned by thick material (Sec. 4.3) */
     float j_bg;            /* background intensity entering at the ray ends */
-    int32_t bins_per_pass; /* ray segments held in LDS per walk pass; 0 = automatic */
+    int32_t bins_per_pass; /* ray segments per walk pass (at most 16); 0 = automatic */
     int32_t chunk;         /* targets taken per work-queue grab; 0 = automatic */
-    int32_t blocks_per_cu; /* persistent blocks per compute unit; 0 = automatic */
+    int32_t waves_per_block; /* persistent waves per block (one target per wave); 0 = as
+                                many as the LDS holds */
 } tr_trace_params;
 
 /* Trace all cells of the tree: J (device float[n_cells], IRXE), F (device float[3][n],

@@ -18,9 +18,10 @@ struct RayTable {
     int n_side = 0, cube_m = 0;
     int16_t *table = nullptr; // [6][M][M] pixel ids
     float4 *dirs = nullptr;   // [npix] unit vectors
-    int tile_rays = 0;        // rays per tile (consecutive NESTED pixels)
-    int n_tiles = 0;
-    float4 *caps = nullptr;   // [n_tiles] bounding cone of each tile: axis, half-angle
+    // [6][M][M] 4-bit entries, two per byte (even cell in the low nibble): side of the
+    // largest square of direction cells starting at the cell (towards larger i and j on
+    // its face) that lies in one pixel, capped at 15
+    uint8_t *square = nullptr;
 };
 
 struct tr_ctx {
@@ -36,6 +37,10 @@ struct tr_ctx {
     // grow-only workspace for the dust solve's learned starting points
     float *ws_guess = nullptr;
     int64_t ws_guess_n = 0;
+    // grow-only per-wave accumulators of the ray tracer's optically thick segment content
+    // (kept all-zero between launches: the tracer clears every entry it reads)
+    float4 *ws_thick = nullptr;
+    int64_t ws_thick_n = 0;
 };
 
 struct tr_tree {

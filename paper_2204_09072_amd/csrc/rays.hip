@@ -137,44 +137,40 @@ int tr_get_table(tr_ctx *ctx, int n_side, int cube_m, RayTable **out) {
         hipFree(rt.dirs);
         return tr_fail(ctx, TR_EHIP, "table kernels failed to launch");
     }
-    // Tiles of rays processed one after another by the trace kernel: all rays when there
-    // are at most 64, otherwise groups of 16 consecutive NESTED pixels (one base pixel at
-    // N_side = 4, a quarter of one at N_side = 8).  Each tile gets a cone that contains
-    // every direction whose direction cell maps into the tile: the widest angle from the
-    // tile axis to a member pixel centre, plus 1.5 pixel widths and 1.5 direction cells.
-    rt.tile_rays = npix <= 64 ? npix : 16;
-    rt.n_tiles = npix / rt.tile_rays;
-    std::vector<float4> d(npix), caps(rt.n_tiles);
-    if (hipMemcpyAsync(d.data(), rt.dirs, sizeof(float4) * npix, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+    // Uniform squares of direction cells, found on the host from the pixel table:
+    // side(i, j) = 1 + min(side(i+1, j), side(i, j+1), side(i+1, j+1)) when the 2x2 cells at
+    // (i, j) share one pixel, else 1 (the classic largest-square recurrence).
+    std::vector<int16_t> pix(ne);
+    if (hipMemcpyAsync(pix.data(), rt.table, sizeof(int16_t) * ne, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
         hipFree(rt.table);
         hipFree(rt.dirs);
-        return tr_fail(ctx, TR_EHIP, "ray directions readback failed");
+        return tr_fail(ctx, TR_EHIP, "direction-cell table readback failed");
     }
-    for (int t = 0; t < rt.n_tiles; ++t) {
-        double c[3] = {0, 0, 0};
-        for (int h = t * rt.tile_rays; h < (t + 1) * rt.tile_rays; ++h) {
-            c[0] += d[h].x; c[1] += d[h].y; c[2] += d[h].z;
-        }
-        double nrm = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-        double rho = kPi; // whole sphere: no culling
-        if (rt.n_tiles > 1 && nrm > 1e-6) {
-            for (int a = 0; a < 3; ++a) c[a] /= nrm;
-            double worst = 0.0;
-            for (int h = t * rt.tile_rays; h < (t + 1) * rt.tile_rays; ++h) {
-                double dot = c[0] * d[h].x + c[1] * d[h].y + c[2] * d[h].z;
-                worst = std::fmax(worst, std::acos(std::fmin(1.0, std::fmax(-1.0, dot))));
+    const int M = cube_m;
+    std::vector<uint8_t> side(ne), nib((ne + 1) / 2, 0);
+    for (int f = 0; f < 6; ++f)
+        for (int i = M - 1; i >= 0; --i)
+            for (int j = M - 1; j >= 0; --j) {
+                const int64_t e = ((int64_t)f * M + i) * M + j;
+                int v = 1;
+                if (i + 1 < M && j + 1 < M) {
+                    const int64_t ei = e + M, ej = e + 1, eij = e + M + 1;
+                    if (pix[e] == pix[ei] && pix[e] == pix[ej] && pix[e] == pix[eij]) {
+                        int m = side[ei] < side[ej] ? side[ei] : side[ej];
+                        m = m < side[eij] ? m : side[eij];
+                        v = 1 + m;
+                    }
+                }
+                side[e] = (uint8_t)(v > 15 ? 15 : v);
             }
-            rho = worst + 1.5 * std::sqrt(4.0 * kPi / npix) + 1.5 * (kPi / 2.0) / cube_m;
-        }
-        caps[t] = make_float4((float)c[0], (float)c[1], (float)c[2], (float)rho);
-    }
-    if (hipMalloc(&rt.caps, sizeof(float4) * rt.n_tiles) != hipSuccess ||
-        hipMemcpy(rt.caps, caps.data(), sizeof(float4) * rt.n_tiles, hipMemcpyHostToDevice) != hipSuccess) {
+    for (int64_t e = 0; e < ne; ++e) nib[e >> 1] |= (uint8_t)(side[e] << (4 * (e & 1)));
+    if (hipMalloc(&rt.square, nib.size()) != hipSuccess ||
+        hipMemcpy(rt.square, nib.data(), nib.size(), hipMemcpyHostToDevice) != hipSuccess) {
         hipFree(rt.table);
         hipFree(rt.dirs);
-        hipFree(rt.caps);
-        return tr_fail(ctx, TR_ENOMEM, "tile cones");
+        hipFree(rt.square);
+        return tr_fail(ctx, TR_ENOMEM, "uniform-square table");
     }
     ctx->tables[key] = rt;
     *out = &ctx->tables[key];

@@ -39,10 +39,11 @@ extern "C" void tr_ctx_destroy(tr_ctx *c) {
     for (auto &kv : c->tables) {
         hipFree(kv.second.table);
         hipFree(kv.second.dirs);
-        hipFree(kv.second.caps);
+        hipFree(kv.second.square);
     }
     hipFree(c->d_ctl);
     hipFree(c->ws_guess);
+    hipFree(c->ws_thick);
     hipHostFree(c->h_err);
     delete c;
 }

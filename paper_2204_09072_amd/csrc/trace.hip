@@ -1,10 +1,13 @@
 // Backward ray tracing of the diffuse infrared field (Sec. 4.2-4.5 of Klepitko et al.).
 //
 // One wavefront per target cell, persistent: waves take targets from a global work
-// counter.  For every target the ray segments (HEALPix pixel x radial evaluation point)
-// live in LDS.  To keep several waves resident per CU the segments are processed in
+// counter.  For every target the optically thin content of the ray segments (HEALPix
+// pixel x radial evaluation point: L_thin, A_thin) lives in LDS; the optically thick
+// content (L V, A, V and Q of thick material), which only a small minority of nodes
+// carries, goes to a per-wave accumulator in global memory with a presence bit per
+// segment in LDS.  To keep many waves resident per CU the segments are processed in
 // passes of `bins_per_pass` radial points; each pass re-walks the octree, pruning
-// subtrees whose material cannot map into the pass, maps the accepted nodes with LDS
+// subtrees whose material cannot map into the pass, maps the accepted nodes with
 // atomics and then integrates the pass outwards with one lane per ray, carrying the
 // extinction and an open merged segment to the next pass.
 //
@@ -13,18 +16,28 @@
 // opening test, the pruning test and the radial bin search are exact integer
 // comparisons; the bin search takes a float estimate and falls back to 64-bit integers
 // only within rounding distance of a bin edge.  Accepted nodes that touch the pass are
-// compacted into an LDS queue and mapped 64 at a time, so the 8-point angular kernel runs
-// with every lane busy.  A block holds several such waves; they share one copy of the
-// direction-cell table in LDS when the pixel ids fit a byte.
+// compacted into one of two LDS queues and mapped 64 at a time, so the 8-point angular
+// kernel runs with every lane busy on the same code path: nodes whose eight sub-points
+// all fall on one cube face take a short path (two reciprocals for the eight points,
+// and a single pixel when the points' direction cells lie inside one uniform square of
+// the pixel table), the rest the general one.  A block holds several such waves; they
+// share one copy of the direction-cell tables in LDS when the pixel ids fit a byte.
 #include "common.hpp"
 
 namespace {
 
 constexpr float kPiF = 3.14159265358979f;
-constexpr int kStack = 640; // ranges per wave; the walk needs at most 56 * depth + 8
-constexpr int kQueue = 128; // accepted nodes waiting to be mapped (< 64 + 64)
+// accepted nodes waiting to be mapped: the one-face queue grows up from 0, the general one
+// down from kQueue - 1; each holds < 64 entries before a walk step adds at most 64
+constexpr int kQueue = 192;
 constexpr int kFields = 6;  // L_thin, A_thin, L_thick*V, A_thick, V_thick, Q
+constexpr int kThin = 2;    // fields held in LDS: L_thin, A_thin
+constexpr int kMaxBp = 16;  // segments per pass: merge flags in bits 0-15 of a ray's flag
+                            // word, thick-content flags in bits 16-31
 
+// ranges on a wave's walk stack: each step pops up to 8 ranges and pushes at most 64,
+// so at most 56 per level of the tree stay behind
+__host__ __device__ inline int stack_size(int depth) { return 56 * depth + 8; }
 struct TraceArgs {
     const int4 *nodes;   // packed walk records
     const float4 *q;     // node content
@@ -34,9 +47,11 @@ struct TraceArgs {
     const float *cell_tau;
     const float *cell_src;
     const int16_t *table;
+    const uint8_t *square; // uniform-square sides, 4 bits per direction cell
     const float4 *dirs;
     int *work;
     int *err;
+    float4 *thick;  // [waves][npix][bp] thick content accumulators, all-zero between uses
     float *J, *F, *u_rad;
     int32_t *counters;
     int64_t n_cells;
@@ -54,28 +69,28 @@ struct TraceArgs {
     float omega;
     float j_bg;
     float c_light;
+    int kstack;     // ranges per wave stack
+    int per_block;  // waves per block
     int lds_wave;   // bytes of LDS per wave
-    int lds_table;  // bytes of the shared table (0: read the table from global memory)
+    int lds_table;  // bytes of the shared tables (0: read the tables from global memory)
 };
 
 struct LdsLayout {
-    int bins, flg, stk, qnode, qpk, qbeta, total;
+    int bins, flg, stk, qnode, qpk, total;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int npix, int bp, bool count) {
+__host__ __device__ inline LdsLayout lds_layout(int npix, int bp, int kstack, bool count) {
     LdsLayout L;
     int o = 0;
     L.bins = o;
-    o += count ? 0 : npix * bp * kFields * 4;
+    o += count ? 0 : npix * bp * kThin * 4;
     L.flg = o;
     o += count ? 0 : npix * 4;
     L.stk = o;
-    o += kStack * 4;
+    o += kstack * 4;
     L.qnode = o;
     o += count ? 0 : kQueue * 4;
     L.qpk = o;
-    o += count ? 0 : kQueue * 4;
-    L.qbeta = o;
     o += count ? 0 : kQueue * 4;
     L.total = (o + 15) & ~15;
     return L;
@@ -154,16 +169,31 @@ __device__ __forceinline__ void cswap(int &a, int &b) {
     b = hi;
 }
 
+// True when the eight sub-points d + (+-h, +-h, +-h) of a node all have the largest
+// component on the axis (and with the sign) of the centre offset d, with cube_cell's
+// tie rule: then they share one cube face.
+__device__ __forceinline__ bool one_face(int dx, int dy, int dz, int h) {
+    const int ax = abs(dx), ay = abs(dy), az = abs(dz), h2 = 2 * h;
+    if (ax >= ay && ax >= az) return ax - h2 >= max(ay, az);
+    if (ay >= az) return ay - h2 > ax && ay - h2 >= az;
+    return az - h2 > max(ax, ay);
+}
+
 // Queue record of an accepted node: pk = content segment (i - a + 1, 0 = none) | first
 // merge flag << 6 | end of merge flags << 12 (both relative to the pass) | leaf << 18 |
-// depth << 19; beta = R_i^2 / r^2 (radial kernel).
+// depth << 19.
 //
 // Map queued nodes (Sec. 4.2.1/4.2.2): one lane per node, the angular kernel from the node
-// cube's 2x2x2 sub-points, one LDS update per distinct pixel.
-template <bool LDS_TABLE>
+// cube's 2x2x2 sub-points, one LDS update per distinct pixel.  ONE_FACE: every node of the
+// batch has its sub-points on one cube face (one_face), so the eight direction cells are
+// (i(a, m), j(b, m)) for the two minor offsets a, b = centre +- h and the two major
+// magnitudes m = |centre| -+ h: four quotients per minor axis instead of eight, and when
+// the cells' bounding square lies inside one uniform square of the table the node maps
+// whole to one pixel.
+template <bool LDS_TABLE, bool ONE_FACE>
 __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *qnode, const uint32_t *qpk,
-                                          const float *qbeta, int4 c256, const uint8_t *tab8, float *bins,
-                                          uint32_t *flg) {
+                                          int pass_a, int4 c256, const uint8_t *tab8, const uint8_t *sqt,
+                                          float *bins, uint32_t *flg, float4 *thick) {
     uint32_t starts = 0;
     int pix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     float Lt = 0, At = 0, LVk = 0, Ak = 0, Vk = 0, beta = 0;
@@ -172,7 +202,6 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
     if (e >= 0) {
         const int node = qnode[e];
         const uint32_t pk = qpk[e];
-        beta = qbeta[e];
         const bool leaf = (pk >> 18) & 1u;
         const int s = A.root_edge >> ((pk >> 19) & 15u);
         seg = (int)(pk & 63u) - 1;
@@ -193,23 +222,76 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             Vk = __int_as_float(p.w);
         }
         const int dx = p.x - c256.x, dy = p.y - c256.y, dz = p.z - c256.z;
-        const int h = 64 * s;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int cx = dx + ((k & 1) ? h : -h), cy = dy + ((k & 2) ? h : -h), cz = dz + ((k & 4) ? h : -h);
-            const int cell = cube_cell(cx, cy, cz, A.log2m);
-            pix[k] = LDS_TABLE ? (int)tab8[cell] : (int)A.table[cell];
+        if (seg >= 0) {
+            // radial kernel beta = R_i^2 / r^2
+            const int i = seg + pass_a;
+            const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+            const float R2 = (float)(TR_FX * i * i);
+            beta = (R2 * R2) * rcp(fx * fx + fy * fy + fz * fz);
         }
-        // sort the 8 pixel ids (19-comparator network), then mark runs of equal ids
-        cswap(pix[0], pix[2]); cswap(pix[1], pix[3]); cswap(pix[4], pix[6]); cswap(pix[5], pix[7]);
-        cswap(pix[0], pix[4]); cswap(pix[1], pix[5]); cswap(pix[2], pix[6]); cswap(pix[3], pix[7]);
-        cswap(pix[0], pix[1]); cswap(pix[2], pix[3]); cswap(pix[4], pix[5]); cswap(pix[6], pix[7]);
-        cswap(pix[2], pix[4]); cswap(pix[3], pix[5]);
-        cswap(pix[1], pix[4]); cswap(pix[3], pix[6]);
-        cswap(pix[1], pix[2]); cswap(pix[3], pix[4]); cswap(pix[5], pix[6]);
-        starts = 1u;
+        const int h = (TR_FX / 4) * s;
+        auto lookup = [&](int cell) { return LDS_TABLE ? (int)tab8[cell] : (int)A.table[cell]; };
+        bool single = false;
+        if (ONE_FACE) {
+            const int ax = abs(dx), ay = abs(dy), az = abs(dz);
+            int f, dm, da, db;
+            if (ax >= ay && ax >= az) {
+                f = dx < 0 ? 1 : 0; dm = ax; da = dy; db = dz;
+            } else if (ay >= az) {
+                f = dy < 0 ? 3 : 2; dm = ay; da = dx; db = dz;
+            } else {
+                f = dz < 0 ? 5 : 4; dm = az; da = dx; db = dy;
+            }
+            const int m1 = dm - h, m2 = dm + h;
+            const uint32_t n1 = 2u * (uint32_t)m1, n2 = 2u * (uint32_t)m2;
+            const float r1 = rcp((float)n1), r2 = rcp((float)n2);
+            const uint32_t Mm1 = (1u << A.log2m) - 1u;
+            auto q = [&](int a, int m, uint32_t den, float rc) {
+                const uint32_t v = exact_div((uint32_t)(a + m) << A.log2m, den, rc);
+                return v > Mm1 ? Mm1 : v;
+            };
+            const uint32_t ia1 = q(da - h, m1, n1, r1), ib1 = q(da + h, m1, n1, r1);
+            const uint32_t ia2 = q(da - h, m2, n2, r2), ib2 = q(da + h, m2, n2, r2);
+            const uint32_t ja1 = q(db - h, m1, n1, r1), jb1 = q(db + h, m1, n1, r1);
+            const uint32_t ja2 = q(db - h, m2, n2, r2), jb2 = q(db + h, m2, n2, r2);
+            const uint32_t i0 = min(ia1, ia2), i1 = max(ib1, ib2), j0 = min(ja1, ja2), j1 = max(jb1, jb2);
+            const int fb = f << A.log2m;
+            const int base = ((fb + (int)i0) << A.log2m) + (int)j0;
+            const uint32_t side = (uint32_t)(sqt[base >> 1] >> (4 * (base & 1))) & 15u;
+            if (side > max(i1 - i0, j1 - j0)) {
+                pix[0] = lookup(base);
+                single = true;
+            } else {
+                pix[0] = lookup(((fb + (int)ia1) << A.log2m) + (int)ja1);
+                pix[1] = lookup(((fb + (int)ia1) << A.log2m) + (int)jb1);
+                pix[2] = lookup(((fb + (int)ib1) << A.log2m) + (int)ja1);
+                pix[3] = lookup(((fb + (int)ib1) << A.log2m) + (int)jb1);
+                pix[4] = lookup(((fb + (int)ia2) << A.log2m) + (int)ja2);
+                pix[5] = lookup(((fb + (int)ia2) << A.log2m) + (int)jb2);
+                pix[6] = lookup(((fb + (int)ib2) << A.log2m) + (int)ja2);
+                pix[7] = lookup(((fb + (int)ib2) << A.log2m) + (int)jb2);
+            }
+        } else {
 #pragma unroll
-        for (int k = 1; k < 8; ++k) starts |= (pix[k] != pix[k - 1] ? 1u : 0u) << k;
+            for (int k = 0; k < 8; ++k) {
+                const int cx = dx + ((k & 1) ? h : -h), cy = dy + ((k & 2) ? h : -h), cz = dz + ((k & 4) ? h : -h);
+                pix[k] = lookup(cube_cell(cx, cy, cz, A.log2m));
+            }
+        }
+        if (single) {
+            starts = 1u;
+        } else {
+            // sort the 8 pixel ids (19-comparator network), then mark runs of equal ids
+            cswap(pix[0], pix[2]); cswap(pix[1], pix[3]); cswap(pix[4], pix[6]); cswap(pix[5], pix[7]);
+            cswap(pix[0], pix[4]); cswap(pix[1], pix[5]); cswap(pix[2], pix[6]); cswap(pix[3], pix[7]);
+            cswap(pix[0], pix[1]); cswap(pix[2], pix[3]); cswap(pix[4], pix[5]); cswap(pix[6], pix[7]);
+            cswap(pix[2], pix[4]); cswap(pix[3], pix[5]);
+            cswap(pix[1], pix[4]); cswap(pix[3], pix[6]);
+            cswap(pix[1], pix[2]); cswap(pix[3], pix[4]); cswap(pix[5], pix[6]);
+            starts = 1u;
+#pragma unroll
+            for (int k = 1; k < 8; ++k) starts |= (pix[k] != pix[k - 1] ? 1u : 0u) << k;
+        }
     }
     // one LDS update per distinct pixel; the loop runs as often as the busiest lane needs
     while (__ballot(starts != 0u)) {
@@ -221,19 +303,22 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
 #pragma unroll
             for (int j = 1; j < 8; ++j) px = k == j ? pix[j] : px;
             const float al = 0.125f * (float)(kn - k);
+            uint32_t fl = fbits;
             if (seg >= 0) {
-                float *bb = bins + (px * A.bp + seg) * kFields;
+                float *bb = bins + (px * A.bp + seg) * kThin;
                 const float ab = al * beta;
                 if (Lt != 0.0f) atomicAdd(bb + 0, ab * Lt);
                 if (At != 0.0f) atomicAdd(bb + 1, ab * At);
                 if (Vk > 0.0f) {
-                    atomicAdd(bb + 2, al * LVk);
-                    atomicAdd(bb + 3, al * Ak);
-                    atomicAdd(bb + 4, al * Vk);
-                    atomicAdd(bb + 5, ab * Vk);
+                    float *tk = reinterpret_cast<float *>(thick + px * A.bp + seg);
+                    atomicAdd(tk + 0, al * LVk);
+                    atomicAdd(tk + 1, al * Ak);
+                    atomicAdd(tk + 2, al * Vk);
+                    atomicAdd(tk + 3, ab * Vk);
+                    fl |= 1u << (16 + seg);
                 }
             }
-            if (fbits) atomicOr(flg + px, fbits);
+            if (fl) atomicOr(flg + px, fl);
         }
     }
 }
@@ -273,14 +358,14 @@ __device__ __forceinline__ void integrate_segment(const float *s, int i, float o
 }
 
 template <int NSLOT, bool COUNT, bool LDS_TABLE>
-__device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_t *tab8) {
-    const LdsLayout LL = lds_layout(A.npix, A.bp, COUNT);
+__device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_t *tab8, const uint8_t *sqt,
+                             float4 *thick) {
+    const LdsLayout LL = lds_layout(A.npix, A.bp, A.kstack, COUNT);
     float *bins = reinterpret_cast<float *>(lds + LL.bins);
     uint32_t *flg = reinterpret_cast<uint32_t *>(lds + LL.flg);
     uint32_t *stk = reinterpret_cast<uint32_t *>(lds + LL.stk);
     int *qnode = reinterpret_cast<int *>(lds + LL.qnode);
     uint32_t *qpk = reinterpret_cast<uint32_t *>(lds + LL.qpk);
-    float *qbeta = reinterpret_cast<float *>(lds + LL.qbeta);
     const int lane = lane_id();
     const int tid = A.targets[ti];
     const int4 tr = A.nodes[tid];
@@ -307,14 +392,14 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
         const int a4 = lo_cut * lo_cut, b4 = hi_cut * hi_cut; // R_a^2, R_b^2 in lattice units
         const bool last = P.b > A.n_bins;
         if (!COUNT) {
-            const int nf = A.npix * A.bp * kFields;
+            const int nf = A.npix * A.bp * kThin;
             for (int k = lane; k < nf; k += 64) bins[k] = 0.0f;
             for (int k = lane; k < A.npix; k += 64) flg[k] = 0u;
         }
         if (lane == 0) stk[0] = 0u; // the root: first node 0, one node
-        int sp = 1, qn = 0;
+        int sp = 1, qf = 0, qs = 0; // stack depth, one-face and general queue lengths
         wave_sync();
-        while (sp > 0 || qn > 0) {
+        while (sp > 0 || qf > 0 || qs > 0) {
             if (sp > 0) {
                 const int npop = sp < 8 ? sp : 8;
                 const int r = lane >> 3, k = lane & 7;
@@ -322,9 +407,8 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                 sp -= npop;
                 wave_sync();
                 const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
-                bool open = false, enq = false;
+                bool open = false, enq = false, face1 = false;
                 uint32_t push = 0, pk = 0;
-                float beta = 0.0f;
                 if (node >= 0) {
                     const int4 nd = A.nodes[node];
                     const int depth = (nd.x >> 16) & 15;
@@ -418,9 +502,7 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                                     pk = (content ? (uint32_t)(i - P.a + 1) : 0u) | ((uint32_t)k0 << 6) |
                                          ((uint32_t)k1 << 12) | ((leaf ? 1u : 0u) << 18) |
                                          ((uint32_t)depth << 19);
-                                    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-                                    const float R2 = (float)(TR_FX * i * i);
-                                    beta = (R2 * R2) * rcp(fx * fx + fy * fy + fz * fz);
+                                    face1 = one_face(dx, dy, dz, (TR_FX / 4) * s);
                                 }
                             }
                         }
@@ -430,36 +512,47 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                 const uint64_t bal = __ballot(open);
                 const int pos = __builtin_popcountll(bal & below);
                 const int npush = __builtin_popcountll(bal);
-                if (open && sp + pos < kStack) stk[sp + pos] = push;
-                if (sp + npush > kStack) {
+                if (open && sp + pos < A.kstack) stk[sp + pos] = push;
+                if (sp + npush > A.kstack) {
                     if (lane == 0) atomicOr(A.err, 4);
-                    sp = kStack;
+                    sp = A.kstack;
                 } else {
                     sp += npush;
                 }
                 if (!COUNT) {
-                    const uint64_t qb = __ballot(enq);
+                    const uint64_t fb = __ballot(enq && face1), gb = __ballot(enq && !face1);
                     if (enq) {
-                        const int qp = qn + __builtin_popcountll(qb & below);
+                        const int qp = face1 ? qf + __builtin_popcountll(fb & below)
+                                             : kQueue - 1 - qs - __builtin_popcountll(gb & below);
                         qnode[qp] = node;
                         qpk[qp] = pk;
-                        qbeta[qp] = beta;
                     }
-                    qn += __builtin_popcountll(qb);
+                    qf += __builtin_popcountll(fb);
+                    qs += __builtin_popcountll(gb);
                 }
                 wave_sync();
             }
             if (COUNT) continue;
-            // map a full batch, or whatever is left once the walk of the pass is done
-            if (qn >= 64 || (sp == 0 && qn > 0)) {
-                const int nq = qn >= 64 ? 64 : qn;
-                const int e = lane < nq ? qn - nq + lane : -1;
-                map_queue<LDS_TABLE>(A, e, qnode, qpk, qbeta, c256, tab8, bins, flg);
-                qn -= nq;
+            // map full batches, or whatever is left once the walk of the pass is done
+            if (qf >= 64 || (sp == 0 && qf > 0)) {
+                const int nq = qf >= 64 ? 64 : qf;
+                const int e = lane < nq ? qf - nq + lane : -1;
+                map_queue<LDS_TABLE, true>(A, e, qnode, qpk, P.a, c256, tab8, sqt, bins, flg, thick);
+                qf -= nq;
+                wave_sync();
+            }
+            if (qs >= 64 || (sp == 0 && qs > 0)) {
+                const int nq = qs >= 64 ? 64 : qs;
+                const int e = lane < nq ? kQueue - qs + lane : -1;
+                map_queue<LDS_TABLE, false>(A, e, qnode, qpk, P.a, c256, tab8, sqt, bins, flg, thick);
+                qs -= nq;
                 wave_sync();
             }
         }
         if (COUNT) break;
+        // the thick accumulators' atomics of every lane have been performed at the device
+        // cache before any lane reads them back
+        __threadfence_block();
         // integrate the pass's segments outwards, one lane per ray
 #pragma unroll
         for (int sl = 0; sl < NSLOT; ++sl) {
@@ -467,7 +560,14 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
             if (h >= A.npix) continue;
             const uint32_t fl = flg[h];
             for (int i = P.a; i < P.b; ++i) {
-                const float *v = bins + (h * A.bp + (i - P.a)) * kFields;
+                const float *th = bins + (h * A.bp + (i - P.a)) * kThin;
+                float v[kFields] = {th[0], th[1], 0.0f, 0.0f, 0.0f, 0.0f};
+                if ((fl >> (16 + i - P.a)) & 1u) {
+                    // read and clear the segment's thick content
+                    float *tk = reinterpret_cast<float *>(thick + h * A.bp + (i - P.a));
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) v[2 + f] = atomicExch(tk + f, 0.0f);
+                }
                 if (R.run_i[sl] == 0) {
                     R.run_i[sl] = i;
 #pragma unroll
@@ -545,13 +645,18 @@ template <int NSLOT, bool COUNT, bool LDS_TABLE>
 __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
     extern __shared__ __align__(16) char smem[];
     const uint8_t *tab8 = reinterpret_cast<const uint8_t *>(smem);
+    const int ncell = 6 << (2 * A.log2m);
+    const uint8_t *sqt = A.square;
     if (LDS_TABLE) {
         uint8_t *t = reinterpret_cast<uint8_t *>(smem);
-        const int ne = 6 << (2 * A.log2m);
-        for (int k = threadIdx.x; k < ne; k += blockDim.x) t[k] = (uint8_t)A.table[k];
+        for (int k = threadIdx.x; k < ncell; k += blockDim.x) t[k] = (uint8_t)A.table[k];
+        for (int k = threadIdx.x; k < ncell / 2; k += blockDim.x) t[ncell + k] = A.square[k];
+        sqt = t + ncell;
         __syncthreads();
     }
     char *lds = smem + A.lds_table + (threadIdx.x >> 6) * A.lds_wave;
+    float4 *thick = COUNT ? nullptr
+                          : A.thick + (int64_t)(blockIdx.x * A.per_block + (threadIdx.x >> 6)) * A.npix * A.bp;
     // XCD-aware work distribution: blocks are dispatched round-robin over the 8 XCDs, so
     // block b runs on XCD b % 8; each XCD takes targets from its own contiguous range of
     // the (Morton-ordered) target list and keeps that region of the tree in its L2.  A
@@ -568,7 +673,7 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
             t0 = __shfl(t0, 0) + lo;
             if (t0 >= hi) break;
             const int t1 = t0 + A.chunk < hi ? t0 + A.chunk : hi;
-            for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE>(A, ti, lds, tab8);
+            for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE>(A, ti, lds, tab8, sqt, thick);
         }
     }
 }
@@ -576,6 +681,11 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
 __global__ void k_zero_int(int *p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
+}
+
+__global__ void k_zero_f32(float *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
 }
 
 // Radiation pressure (Sec. 4.5)
@@ -627,19 +737,24 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     int rc = tr_get_table(ctx, ns, M, &rt);
     if (rc) return rc;
     const int npix = 12 * ns * ns;
+    const bool tab_lds = !count && npix <= 256;
+    const int lds_table = tab_lds ? ((6 * M * M + 3 * M * M + 15) & ~15) : 0;
+    const int kstack = stack_size(t->D);
+    const int max_waves = npix > 192 ? 4 : 16; // the kernel's launch bound
+    const int lds_cu = 160 * 1024;
     int bp = p->bins_per_pass;
     if (bp <= 0) {
-        // the largest pass with per-wave LDS under 20 KB (several waves per CU)
-        bp = t->n_bins;
-        while (bp > 1 && lds_layout(npix, bp, false).total > 20 * 1024) --bp;
+        // the longest pass that still lets a full block of waves share the CU's LDS
+        bp = t->n_bins < kMaxBp ? t->n_bins : kMaxBp;
+        while (bp > 1 && lds_table + max_waves * lds_layout(npix, bp, kstack, false).total > lds_cu) --bp;
     }
     if (bp > t->n_bins) bp = t->n_bins;
-    if (bp > 31) bp = 31;
+    if (bp > kMaxBp) bp = kMaxBp;
     if (bp < 1) bp = 1;
     TraceArgs A;
     A.nodes = t->packed; A.q = t->q; A.pcol = t->pcol;
     A.targets = t->targets; A.leaf_cell = t->leaf_cell; A.cell_tau = t->cell_tau; A.cell_src = t->cell_src;
-    A.table = rt->table; A.dirs = rt->dirs;
+    A.table = rt->table; A.square = rt->square; A.dirs = rt->dirs;
     A.work = ctx->d_ctl; A.err = ctx->d_ctl + 16;
     A.J = J; A.F = F; A.u_rad = u_rad; A.counters = counters;
     A.n_cells = t->n_cells; A.n_targets = (int)t->n_cells; A.root_edge = (int)t->root_edge;
@@ -654,16 +769,36 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     A.omega = (float)(4.0 * 3.14159265358979323846 / npix);
     A.j_bg = p->j_bg;
     A.c_light = (float)t->c_light;
-    A.lds_wave = lds_layout(npix, bp, count).total;
-    const bool tab_lds = !count && npix <= 256;
-    A.lds_table = tab_lds ? ((6 * M * M + 15) & ~15) : 0;
-    // waves per block: as many as fit in 160 KB together with the shared table
-    int per_block = p->blocks_per_cu > 0 ? p->blocks_per_cu : (160 * 1024 - A.lds_table) / A.lds_wave;
-    if (per_block > (npix > 192 ? 4 : 16)) per_block = npix > 192 ? 4 : 16;
+    A.kstack = kstack;
+    A.lds_wave = lds_layout(npix, bp, kstack, count).total;
+    A.lds_table = lds_table;
+    // waves per block: as many as fit in the CU's LDS together with the shared tables
+    int per_block = p->waves_per_block > 0 ? p->waves_per_block : (lds_cu - lds_table) / A.lds_wave;
+    if (per_block > max_waves) per_block = max_waves;
     if (per_block < 1) per_block = 1;
-    const size_t lds = (size_t)A.lds_table + (size_t)per_block * A.lds_wave;
-    if (lds > 160 * 1024) return tr_fail(ctx, TR_EINVAL, "LDS per block too large (%zu bytes)", lds);
-    const int grid = ctx->n_cu;
+    A.per_block = per_block;
+    const size_t lds = (size_t)lds_table + (size_t)per_block * A.lds_wave;
+    if (lds > (size_t)lds_cu) return tr_fail(ctx, TR_EINVAL, "LDS per block too large (%zu bytes)", lds);
+    // one block per CU when the tables sit in LDS; otherwise as many blocks as fit
+    int blocks_cu = tab_lds ? 1 : (int)(lds_cu / lds);
+    if (blocks_cu > 8) blocks_cu = 8;
+    const int grid = ctx->n_cu * blocks_cu;
+    A.thick = nullptr;
+    if (!count) {
+        const int64_t need = (int64_t)grid * per_block * npix * bp;
+        if (ctx->ws_thick_n < need) {
+            hipFree(ctx->ws_thick);
+            ctx->ws_thick = nullptr;
+            ctx->ws_thick_n = 0;
+            if (hipMalloc(&ctx->ws_thick, sizeof(float4) * need) != hipSuccess)
+                return tr_fail(ctx, TR_ENOMEM, "thick-content accumulators (%lld bytes)",
+                               (long long)(sizeof(float4) * need));
+            k_zero_f32<<<(int)tr_div_up(4 * need, 256 * 64), 256, 0, ctx->stream>>>(
+                reinterpret_cast<float *>(ctx->ws_thick), 4 * need);
+            ctx->ws_thick_n = need;
+        }
+        A.thick = ctx->ws_thick;
+    }
     k_zero_int<<<1, 64, 0, ctx->stream>>>(ctx->d_ctl, 8);
     const dim3 blk(64 * per_block);
 #define LAUNCH(NS_, C_, T_) hipLaunchKernelGGL((k_trace<NS_, C_, T_>), dim3(grid), blk, lds, ctx->stream, A)
