@@ -123,6 +123,96 @@ def cpu_baseline(w, n_pix, stride, u_rad=None):
     }
 
 
+def _rocpd(paths):
+    """Open every rocprofv3 result database under the given paths (rocpd SQLite)."""
+    import glob
+    import sqlite3
+    dbs = []
+    for p in paths:
+        dbs += sorted(glob.glob(os.path.join(p, "**", "*.db"), recursive=True)) if os.path.isdir(p) else [p]
+    if not dbs:
+        raise SystemExit(f"no rocprofv3 database under {paths}")
+    return [sqlite3.connect(d) for d in dbs]
+
+
+def summarize_kernels(paths):
+    """Text summary of a `rocprofv3 --kernel-trace --stats` run: per-kernel calls and durations
+    (the database's top_kernels view holds microseconds)."""
+    rows = {}
+    for c in _rocpd(paths):
+        for name, calls, total, avg, _ in c.execute("select * from top_kernels"):
+            r = rows.setdefault(name, [0, 0.0])
+            r[0] += calls
+            r[1] += total
+    tot = sum(r[1] for r in rows.values()) or 1.0
+    out = [f"{'calls':>6} {'total ms':>12} {'avg ms':>12} {'share':>7}  kernel"]
+    for name, (calls, total) in sorted(rows.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"{calls:6d} {total / 1e3:12.3f} {total / calls / 1e3:12.3f} {100 * total / tot:6.2f}%  {name[:110]}")
+    return "\n".join(out)
+
+
+def pmc_per_dispatch(paths):
+    """{(kernel, dispatch): {counter: value}} from `rocprofv3 --pmc` runs."""
+    res = {}
+    for c in _rocpd(paths):
+        for kname, disp, cname, val in c.execute(
+                "select kernel_name, dispatch_id, counter_name, value from counters_collection"):
+            res.setdefault((kname, disp), {})
+            res[(kname, disp)][cname] = res[(kname, disp)].get(cname, 0.0) + val
+    return res
+
+
+def write_traffic(workload, fetch_paths, write_paths, calib_bytes, out_paths):
+    """HBM bytes per trace launch from FETCH_SIZE and WRITE_SIZE runs of --traffic-probe,
+    each scaled by the same counter's reading for a plain copy of known size."""
+    def pick(paths, counter):
+        d = pmc_per_dispatch(paths)
+        trace = [v[counter] for (k, _), v in d.items() if "k_trace<" in k and "true" not in k.split(",")[1]]
+        other = [v[counter] for (k, _), v in d.items() if "k_trace" not in k]
+        if not trace or not other:
+            raise SystemExit(f"{counter}: trace or calibration dispatch missing")
+        return float(np.mean(trace)), float(max(other))
+    f_trace, f_copy = pick(fetch_paths, "FETCH_SIZE")
+    w_trace, w_copy = pick(write_paths, "WRITE_SIZE")
+    kf, kw = calib_bytes / (f_copy * 1024.0), calib_bytes / (w_copy * 1024.0)
+    info = {"workload": workload, "kernel": "k_trace", "trace_hip_sha": kernel_source_hash(),
+            "fetch_kib_per_launch": f_trace, "write_kib_per_launch": w_trace,
+            "copy_bytes": calib_bytes, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
+            "fetch_scale": kf, "write_scale": kw,
+            "bytes_per_launch": f_trace * 1024.0 * kf + w_trace * 1024.0 * kw}
+    for p in out_paths:
+        with open(p, "w") as f:
+            json.dump(info, f, indent=1)
+    return info
+
+
+CALIB_BYTES = 1 << 30   # plain device-to-device copy used to scale the byte counters
+
+
+def traffic_probe(name):
+    """One trace launch of the workload preceded by a plain 1 GiB device copy (run under
+    rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)."""
+    import torch
+    import paper_2204_09072_amd as T
+    from paper_2204_09072_amd.run import params_of, upload
+    w = make_workload(name)
+    ctx = T.Context(0)
+    dev = upload(w)
+    src = torch.ones(CALIB_BYTES // 4, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    tree = T.build_tree(ctx, w.nb, w.max_level, w.blocks, w.x0, w.box_len, dev["rho"], dev["kappa"],
+                        dev["t_dust"], w.stars, w.units[0], w.units[1])
+    n = w.n_cells
+    J = torch.empty(n, device="cuda")
+    F = torch.empty((3, n), device="cuda")
+    T.trace_rays(ctx, tree, params_of(w), J, F, None)
+    ctx.sync()
+    log(f"traffic probe {name}: one trace launch done")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,11 +225,30 @@ def main():
     ap.add_argument("--bins-per-pass", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one calibration copy and one trace launch, for rocprofv3 --pmc runs")
+    ap.add_argument("--summarize", nargs="+", metavar="DIR",
+                    help="print the per-kernel summary of rocprofv3 --kernel-trace --stats output")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/trace_<workload>_traffic.json from two --pmc runs")
+    ap.add_argument("--traffic-out", nargs="*", default=None)
     args = ap.parse_args()
+    if args.summarize:
+        print(summarize_kernels(args.summarize))
+        return
+    if args.write_traffic:
+        outs = args.traffic_out or [os.path.join(ROOT, "profiles", f"trace_{args.workload}_traffic.json")]
+        print(json.dumps(write_traffic(args.workload, [args.write_traffic[0]], [args.write_traffic[1]],
+                                       CALIB_BYTES, outs)))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.traffic_probe:
+        traffic_probe(args.workload)
+        return
 
     import torch
     import paper_2204_09072_amd as T
