@@ -14,7 +14,11 @@
  *   dust equilibrium ...... Sec. 4.6, App. E
  *
  * Where the paper is silent or ambiguous the reading taken is stated next to the code
- * that implements it.  Only the tests, the smoke check and the benchmark's CPU-baseline
+ * that implements it.
+ *
+ * Parity unpinned: the host-cell source terms J_src (Sec. 4.4) and P_src (Sec. 4.5) follow
+ * a reading of definitions the paper leaves open (the source volume and area); nothing
+ * outside this code fixes their values, so only their limits are tested.  Only the tests, the smoke check and the benchmark's CPU-baseline
  * leg load this code; it shares nothing with the library under paper_2204_09072_amd/.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared  (no fast-math: the fixed

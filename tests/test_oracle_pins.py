@@ -5,12 +5,21 @@ the passage of Klepitko et al. (MNRAS 2023) it follows.  A plausible mistake in 
 oracle (a dropped term, a wrong sign or index, the literal beta = r^2/R_i^2, a wrong
 extinction product) fails at least one of them.
 """
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
 from workloads.synth import cell_centres, cell_sizes
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    """Numbers the paper prints, one row per line (see each file's header for the passage)."""
+    return np.loadtxt(os.path.join(GOLDEN, name), comments="#", ndmin=2)
 
 
 # ----------------------------------------------------------------------------------
@@ -197,6 +206,54 @@ def test_point_source_beer_lambert_staircase(kap, tol):
     assert q.std() < 3 * tol
 
 
+def test_point_source_fitted_opacity_as_printed():
+    """Sec. 5.1: an exponential fit to J r^2 of a point source in a uniform absorber
+    recovers the opacity with a small overshoot of the extinction; the paper prints
+    kappa_fit = 1.03 and 10.24 for kappa = 1 and 10 with 48 rays.  Same optical depth per
+    box edge here (kappa rho L = 0.31 and 3.1 in code units), 64^3 cells, N_side = 2: the
+    fitted opacity is within the paper's own deviation of the true one."""
+    n = 64
+    rows = golden("point_source_kappa.txt")
+    for (k_true, k_fit), tau_box in zip(rows, (0.3086, 3.086)):
+        w = W.point_source_box(n, tau_box, n_side=2)
+        t = oracle.Tree(w)
+        x = cell_centres(w)
+        r = np.linalg.norm(x - (0.5 + 0.25 / n), axis=1)
+        cells = np.nonzero((r > 0.1) & (r < 0.45))[0][::7]
+        J, _ = t.trace(oracle.params(2), cells=cells)
+        y = np.log(J * r[cells] ** 2 * 16 * np.pi ** 2)
+        A = np.vstack([np.ones(len(cells)), -r[cells]]).T
+        _, k = np.linalg.lstsq(A, y, rcond=None)[0]
+        over = k / tau_box - 1.0
+        assert abs(over) <= k_fit / k_true - 1.0, (k_true, over)
+
+
+def test_planck_opacity_as_printed():
+    """Sec. 2: with no opacity array the b-node opacity is the Planck mean of the printed
+    law; A = rho kappa dV of each leaf recovers it exactly."""
+    rows = golden("planck_opacity.txt")
+    n = 8
+    t3 = np.zeros((n, n, n))
+    flat = t3.reshape(-1)
+    flat[: len(rows)] = rows[:, 0]
+    flat[len(rows):] = 10.0
+    rho, box = 1e-22, 3.0857e18
+    w = W.synth._uniform_workload("planck", np.full((n, n, n), rho), t3, None, 1, box,
+                                  W.CGS_UNITS, 1, np.zeros((0, 4)), cgs=True)
+    t = oracle.Tree(w)
+    ex, f = t.export(), t.export_f64()
+    leaf = np.nonzero(ex["leaf_cell"] >= 0)[0]
+    cell = ex["leaf_cell"][leaf]
+    dv = (box / n) ** 3
+    kap = np.empty(w.n_cells)
+    kap[cell] = f[leaf, 2] * t.u_len ** 2 / (float(np.float32(rho)) * dv)
+    tcell = w.t_dust.astype(np.float64)
+    for T, k in rows:
+        c = np.nonzero(np.isclose(tcell, np.float32(T)))[0]
+        assert len(c) >= 1
+        assert np.allclose(kap[c], k * (np.float64(np.float32(T)) / T) ** (2 if T < 150 else 0), rtol=1e-9, atol=0)
+
+
 def test_thin_isothermal_telescoping_identity():
     """All cells thin at one temperature: J = B (1 - <e^{-tau_h}>_h) exactly (the
     telescoping of eq. fthin with the extinction product; App. B's limits follow)."""
@@ -278,6 +335,10 @@ def test_thick_split_over_two_and_three_rays():
     assert one == pytest.approx(beta * V ** (2 / 3) / R2, rel=1e-13)
     assert 2 * ray(0.5) / one == pytest.approx(2 ** (1 / 3), rel=1e-12)
     assert 3 * ray(1 / 3) / one == pytest.approx(3 ** (1 / 3), rel=1e-12)
+    # the increases the paper prints (two digits)
+    for rays, inc in golden("thick_split.txt"):
+        k = int(rays)
+        assert abs(k * ray(1.0 / k) / one - 1.0 - inc) < 0.005
 
 
 def test_merge_moves_inverse_square_content():
