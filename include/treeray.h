@@ -121,6 +121,36 @@ typedef struct tr_trace_params {
 int tr_trace_rays(tr_ctx *ctx, const tr_tree *tree, const tr_trace_params *p, float *J,
                   float *F, float *u_rad);
 
+/* Batched ray tracing: many trees (uneven AMR instances, each with its own N_side,
+ * opening angle and outputs) traced by ONE persistent launch whose waves take targets
+ * from the concatenated target lists; the launch is captured once in a HIP graph.
+ * trees: HOST array [n] of tree handles; p: HOST array [n] of parameters (the knobs
+ * bins_per_pass, chunk and waves_per_block of p[0] apply to the whole batch and are what
+ * tr_batch_tune replaces); J, F, u_rad: HOST arrays [n] of device pointers (u_rad or its
+ * entries may be NULL).  At most 4 distinct (N_side, cube_m) per batch.  The batch keeps
+ * the pointers: trees and outputs must outlive it.  Creation synchronises the context's
+ * stream. */
+typedef struct tr_batch tr_batch;
+int tr_batch_create(tr_ctx *ctx, int n, const tr_tree *const *trees, const tr_trace_params *p,
+                    float *const *J, float *const *F, float *const *u_rad, tr_batch **out);
+/* Replay the captured graph on the context's stream (asynchronous; no allocation). */
+int tr_batch_launch(tr_batch *b);
+/* The same work launched directly instead of through the graph (asynchronous). */
+int tr_batch_launch_eager(tr_batch *b);
+/* Autotuner: times the batch on every sample_stride-th target of each instance while
+ * varying segments per pass, waves per block and the work-queue chunk (coordinate
+ * descent), keeps the fastest and re-captures the graph.  Synchronous.  The outputs of
+ * the sampled targets are overwritten. */
+typedef struct tr_batch_tuning {
+    int32_t bins_per_pass, waves_per_block, chunk;
+    float sample_ms; /* time of the tuned launch on the sample */
+} tr_batch_tuning;
+int tr_batch_tune(tr_batch *b, int sample_stride, tr_batch_tuning *best);
+void tr_batch_free(tr_batch *b);
+/* One-shot batched trace (build descriptors, one persistent launch, free); synchronous. */
+int tr_trace_rays_batched(tr_ctx *ctx, int n, const tr_tree *const *trees, const tr_trace_params *p,
+                          float *const *J, float *const *F, float *const *u_rad);
+
 /* Walk statistics of the opening-angle walk per target cell: counters (device
  * int32[n_cells][3] = b-nodes accepted, h-nodes accepted, h-nodes opened). */
 int tr_walk_counts(tr_ctx *ctx, const tr_tree *tree, const tr_trace_params *p,

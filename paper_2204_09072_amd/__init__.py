@@ -52,6 +52,11 @@ class TraceParams(C.Structure):
                 ("bins_per_pass", C.c_int32), ("chunk", C.c_int32), ("waves_per_block", C.c_int32)]
 
 
+class BatchTuning(C.Structure):
+    _fields_ = [("bins_per_pass", C.c_int32), ("waves_per_block", C.c_int32), ("chunk", C.c_int32),
+                ("sample_ms", C.c_float)]
+
+
 class DustParams(C.Structure):
     _fields_ = [("sigma", C.c_double), ("c", C.c_double), ("c_gd", C.c_double), ("xi", C.c_double),
                 ("rel_tol", C.c_float), ("max_iter", C.c_int32)]
@@ -76,6 +81,12 @@ _sig("tr_tree_get_info", _I, [_P, C.POINTER(TreeInfo)])
 _sig("tr_tree_export", _I, [_P, _P, _P, _P, _P, _P, _P, _P])
 _sig("tr_trace_rays", _I, [_P, _P, C.POINTER(TraceParams), _P, _P, _P])
 _sig("tr_walk_counts", _I, [_P, _P, C.POINTER(TraceParams), _P])
+_sig("tr_batch_create", _I, [_P, _I, _P, _P, _P, _P, _P, C.POINTER(_P)])
+_sig("tr_batch_launch", _I, [_P])
+_sig("tr_batch_launch_eager", _I, [_P])
+_sig("tr_batch_tune", _I, [_P, _I, C.POINTER(BatchTuning)])
+_sig("tr_batch_free", None, [_P])
+_sig("tr_trace_rays_batched", _I, [_P, _I, _P, _P, _P, _P, _P])
 _sig("tr_ray_tables", _I, [_P, _I, _I, _P, _P])
 _sig("tr_rad_force", _I, [_P, _P, _P, _P, _P])
 _sig("tr_dust_equilibrium", _I, [_P, C.c_int64, _P, _P, _P, C.POINTER(DustParams), _P, _P, _P])
@@ -124,9 +135,9 @@ class Context:
     def sync(self):
         self.check(_lib.tr_sync(self.h))
 
-    def close(self):
+    def close(self, _destroy=_lib.tr_ctx_destroy):
         if getattr(self, "h", None):
-            _lib.tr_ctx_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -149,9 +160,9 @@ class Tree:
         self.n_bins = info.n_bins
         self.u_len = info.u_len
 
-    def free(self):
+    def free(self, _free=_lib.tr_tree_free):
         if getattr(self, "h", None):
-            _lib.tr_tree_free(self.h)
+            _free(self.h)
             self.h = None
 
     def __del__(self):
@@ -194,6 +205,55 @@ def trace_params(n_side, theta=None, cube_m=0, merge=True, j_bg=0.0, bins_per_pa
 def trace_rays(ctx: Context, tree: Tree, p: TraceParams, J, F, u_rad=None):
     """tr_trace_rays: J [n], F [3, n], u_rad [n] or None (device float32)."""
     ctx.check(_lib.tr_trace_rays(ctx.h, tree.h, C.byref(p), _ptr(J), _ptr(F), _ptr(u_rad)))
+
+
+def _batch_arrays(trees, params, J, F, U):
+    n = len(trees)
+    assert len(params) == n and len(J) == n and len(F) == n
+    th = (_P * n)(*[t.h for t in trees])
+    pa = (TraceParams * n)(*params)
+    ja = (_P * n)(*[_ptr(x) for x in J])
+    fa = (_P * n)(*[_ptr(x) for x in F])
+    ua = None if U is None else (_P * n)(*[_ptr(x) for x in U])
+    return n, th, pa, ja, fa, ua
+
+
+class Batch:
+    """tr_batch: many trees traced by one persistent launch replayed from a HIP graph.
+    trees, params, J, F, U: equal-length lists (U may be None or hold None entries)."""
+
+    def __init__(self, ctx: Context, trees, params, J, F, U=None):
+        self.ctx = ctx
+        self._keep = (list(trees), list(J), list(F), None if U is None else list(U))
+        n, th, pa, ja, fa, ua = _batch_arrays(trees, params, J, F, U)
+        h = _P()
+        ctx.check(_lib.tr_batch_create(ctx.h, n, th, pa, ja, fa, ua, C.byref(h)))
+        self.h = h
+
+    def launch(self):
+        self.ctx.check(_lib.tr_batch_launch(self.h))
+
+    def launch_eager(self):
+        self.ctx.check(_lib.tr_batch_launch_eager(self.h))
+
+    def tune(self, sample_stride=16) -> BatchTuning:
+        out = BatchTuning()
+        self.ctx.check(_lib.tr_batch_tune(self.h, int(sample_stride), C.byref(out)))
+        return out
+
+    def free(self, _free=_lib.tr_batch_free):
+        if getattr(self, "h", None):
+            _free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.free()
+
+
+def trace_rays_batched(ctx: Context, trees, params, J, F, U=None):
+    """tr_trace_rays_batched: one persistent launch over all trees (synchronous)."""
+    n, th, pa, ja, fa, ua = _batch_arrays(trees, params, J, F, U)
+    ctx.check(_lib.tr_trace_rays_batched(ctx.h, n, th, pa, ja, fa, ua))
 
 
 def walk_counts(ctx: Context, tree: Tree, p: TraceParams, counters):
@@ -254,9 +314,9 @@ class Mlp:
         self.ctx.check(_lib.tr_mlp_train_step(self.ctx.h, self.h, int(x.shape[0]), _ptr(x), _ptr(y),
                                               float(lr), _ptr(loss)))
 
-    def free(self):
+    def free(self, _free=_lib.tr_mlp_free):
         if getattr(self, "h", None):
-            _lib.tr_mlp_free(self.h)
+            _free(self.h)
             self.h = None
 
     def __del__(self):

@@ -70,6 +70,7 @@ struct TraceArgs {
     float j_bg;
     float c_light;
     int kstack;     // ranges per wave stack
+    int tab_slot;   // batched launches: which LDS table set the instance uses
     int per_block;  // waves per block
     int lds_wave;   // bytes of LDS per wave
     int lds_table;  // bytes of the shared tables (0: read the tables from global memory)
@@ -678,6 +679,76 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
     }
 }
 
+// Batched launch: many trees (instances) in one persistent grid.  The targets of all
+// instances form one index space (prefix sums `start`, optionally every `stride`-th
+// target); waves take chunks of it exactly as in k_trace and trace each target with its
+// instance's arguments.  The LDS holds one copy of every distinct direction-cell table of
+// the batch.
+constexpr int kMaxTabs = 4;
+
+struct BatchArgs {
+    const TraceArgs *__restrict__ inst; // [n_inst]
+    const int *start;      // [n_inst + 1]
+    int n_inst;
+    int n_total;
+    int stride;
+    int *work;
+    int chunk;
+    int per_block;
+    int lds_wave;
+    int lds_table;
+    int n_tab;
+    const int16_t *tab[kMaxTabs];
+    const uint8_t *sq[kMaxTabs];
+    int tab_off[kMaxTabs];
+    int tab_ncell[kMaxTabs];
+    float4 *thick;
+    int thick_wave; // float4 per wave
+};
+
+template <int NSLOT, bool LDS_TABLE>
+__global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace_batch(BatchArgs B) {
+    extern __shared__ __align__(16) char smem[];
+    if (LDS_TABLE) {
+        for (int s = 0; s < B.n_tab; ++s) {
+            uint8_t *t = reinterpret_cast<uint8_t *>(smem) + B.tab_off[s];
+            const int nc = B.tab_ncell[s];
+            for (int k = threadIdx.x; k < nc; k += blockDim.x) t[k] = (uint8_t)B.tab[s][k];
+            for (int k = threadIdx.x; k < nc / 2; k += blockDim.x) t[nc + k] = B.sq[s][k];
+        }
+        __syncthreads();
+    }
+    char *lds = smem + B.lds_table + (threadIdx.x >> 6) * B.lds_wave;
+    float4 *thick = B.thick + (int64_t)(blockIdx.x * B.per_block + (threadIdx.x >> 6)) * B.thick_wave;
+    const int home = blockIdx.x & 7;
+    const int per = (B.n_total + 7) >> 3;
+    for (int x = 0; x < 8; ++x) {
+        const int r = (home + x) & 7;
+        const int lo = r * per;
+        const int hi = min(lo + per, B.n_total);
+        for (;;) {
+            int t0 = 0;
+            if (lane_id() == 0) t0 = atomicAdd(B.work + r, B.chunk);
+            t0 = __builtin_amdgcn_readfirstlane(t0) + lo;
+            if (t0 >= hi) break;
+            const int t1 = t0 + B.chunk < hi ? t0 + B.chunk : hi;
+            for (int ti = t0; ti < t1; ++ti) {
+                // the instance holding global target ti: start[k] <= ti < start[k + 1]
+                int a = 0, b = B.n_inst;
+                while (b - a > 1) {
+                    const int m = (a + b) >> 1;
+                    if (B.start[m] <= ti) a = m; else b = m;
+                }
+                const int k = __builtin_amdgcn_readfirstlane(a);
+                const TraceArgs &A = B.inst[k];
+                const uint8_t *tab8 = reinterpret_cast<const uint8_t *>(smem) + B.tab_off[A.tab_slot];
+                const uint8_t *sqt = LDS_TABLE ? tab8 + B.tab_ncell[A.tab_slot] : A.square;
+                trace_target<NSLOT, false, LDS_TABLE>(A, (ti - B.start[k]) * B.stride, lds, tab8, sqt, thick);
+            }
+        }
+    }
+}
+
 __global__ void k_zero_int(int *p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -712,11 +783,23 @@ __global__ void k_rad_force(int64_t n, const float *__restrict__ F, const float 
     }
 }
 
-int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float *J, float *F,
-                 float *u_rad, int32_t *counters, bool count) {
-    if (!ctx) return TR_EINVAL;
-    if (!t || !p) return tr_fail(ctx, TR_EINVAL, "tr_trace_rays: null argument");
-    if (!count && (!J || !F)) return tr_fail(ctx, TR_EINVAL, "tr_trace_rays: null output");
+// Validated set-up of one traced tree: the knob-independent kernel arguments.
+struct Inst {
+    TraceArgs A;
+    RayTable *rt = nullptr;
+    int M = 0, npix = 0;
+};
+
+constexpr int kLdsCu = 160 * 1024;
+
+int table_bytes(int M) { return (6 * M * M + 3 * M * M + 15) & ~15; }
+int max_waves_for(int npix) { return npix > 192 ? 4 : 16; } // the kernel's launch bound
+int nslot_for(int npix) { return npix <= 64 ? 1 : (npix <= 192 ? 3 : 12); }
+
+int setup_instance(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float *J, float *F, float *u_rad,
+                   int32_t *counters, bool count, Inst &I) {
+    if (!t || !p) return tr_fail(ctx, TR_EINVAL, "trace: null argument");
+    if (!count && (!J || !F)) return tr_fail(ctx, TR_EINVAL, "trace: null output");
     const int ns = p->n_side;
     if (ns != 1 && ns != 2 && ns != 4 && ns != 8)
         return tr_fail(ctx, TR_EINVAL, "n_side must be 1, 2, 4 or 8 (got %d)", ns);
@@ -732,71 +815,99 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     if (t->n_bins > 63) return tr_fail(ctx, TR_EINVAL, "too many ray segments (%d)", t->n_bins);
     if (t->n_node >= ((int64_t)1 << 29)) return tr_fail(ctx, TR_EINVAL, "too many nodes for the walk stack");
     if (t->root_edge > 2048) return tr_fail(ctx, TR_EINVAL, "grid too fine for the walk's integer ranges");
-    TR_HIP(ctx, hipSetDevice(ctx->device));
-    RayTable *rt = nullptr;
-    int rc = tr_get_table(ctx, ns, M, &rt);
+    if (t->n_cells >= ((int64_t)1 << 31)) return tr_fail(ctx, TR_EINVAL, "too many cells");
+    if (t->ctx != ctx && t->ctx && t->ctx->device != ctx->device)
+        return tr_fail(ctx, TR_EINVAL, "tree lives on another device");
+    int rc = tr_get_table(ctx, ns, M, &I.rt);
     if (rc) return rc;
-    const int npix = 12 * ns * ns;
-    const bool tab_lds = !count && npix <= 256;
-    const int lds_table = tab_lds ? ((6 * M * M + 3 * M * M + 15) & ~15) : 0;
-    const int kstack = stack_size(t->D);
-    const int max_waves = npix > 192 ? 4 : 16; // the kernel's launch bound
-    const int lds_cu = 160 * 1024;
-    int bp = p->bins_per_pass;
-    if (bp <= 0) {
-        // the longest pass that still lets a full block of waves share the CU's LDS
-        bp = t->n_bins < kMaxBp ? t->n_bins : kMaxBp;
-        while (bp > 1 && lds_table + max_waves * lds_layout(npix, bp, kstack, false).total > lds_cu) --bp;
-    }
-    if (bp > t->n_bins) bp = t->n_bins;
-    if (bp > kMaxBp) bp = kMaxBp;
-    if (bp < 1) bp = 1;
-    TraceArgs A;
+    I.M = M;
+    I.npix = 12 * ns * ns;
+    TraceArgs &A = I.A;
+    A = TraceArgs{};
     A.nodes = t->packed; A.q = t->q; A.pcol = t->pcol;
     A.targets = t->targets; A.leaf_cell = t->leaf_cell; A.cell_tau = t->cell_tau; A.cell_src = t->cell_src;
-    A.table = rt->table; A.square = rt->square; A.dirs = rt->dirs;
+    A.table = I.rt->table; A.square = I.rt->square; A.dirs = I.rt->dirs;
     A.work = ctx->d_ctl; A.err = ctx->d_ctl + 16;
     A.J = J; A.F = F; A.u_rad = u_rad; A.counters = counters;
     A.n_cells = t->n_cells; A.n_targets = (int)t->n_cells; A.root_edge = (int)t->root_edge;
-    A.npix = npix; A.log2m = log2m; A.n_bins = t->n_bins; A.bp = bp;
-    A.n_pass = (int)tr_div_up(t->n_bins, bp);
-    A.chunk = p->chunk > 0 ? p->chunk : 4;
+    A.npix = I.npix; A.log2m = log2m; A.n_bins = t->n_bins;
     A.merge = p->merge ? 1 : 0;
     A.th_num2 = (int)(num * num); A.th_den2 = (int)(den * den);
     // 32-bit products are exact when num^2 d^2 and den^2 s^2 stay below 2^31
     const int64_t max_d2 = 3 * t->root_edge * t->root_edge, max_s2 = t->root_edge * t->root_edge;
     A.wide_open = (num * num * max_d2 >= ((int64_t)1 << 31) || den * den * max_s2 >= ((int64_t)1 << 31)) ? 1 : 0;
-    A.omega = (float)(4.0 * 3.14159265358979323846 / npix);
+    A.omega = (float)(4.0 * 3.14159265358979323846 / I.npix);
     A.j_bg = p->j_bg;
     A.c_light = (float)t->c_light;
-    A.kstack = kstack;
-    A.lds_wave = lds_layout(npix, bp, kstack, count).total;
+    A.kstack = stack_size(t->D);
+    A.tab_slot = 0;
+    return TR_OK;
+}
+
+// segments per pass of one instance under a requested value (0 = automatic: the longest
+// pass that lets max_waves waves share the CU's LDS next to `lds_table` bytes of tables)
+int choose_bp(const Inst &I, int want, int lds_table, int max_waves, bool count) {
+    int bp = want;
+    if (bp <= 0) {
+        bp = I.A.n_bins < kMaxBp ? I.A.n_bins : kMaxBp;
+        while (bp > 1 && lds_table + max_waves * lds_layout(I.npix, bp, I.A.kstack, count).total > kLdsCu) --bp;
+    }
+    if (bp > I.A.n_bins) bp = I.A.n_bins;
+    if (bp > kMaxBp) bp = kMaxBp;
+    if (bp < 1) bp = 1;
+    return bp;
+}
+
+void set_bp(Inst &I, int bp, bool count) {
+    I.A.bp = bp;
+    I.A.n_pass = (int)tr_div_up(I.A.n_bins, bp);
+    I.A.lds_wave = lds_layout(I.npix, bp, I.A.kstack, count).total;
+}
+
+// grow-only per-wave thick-content accumulators, kept all-zero between uses
+int ensure_thick(tr_ctx *ctx, int64_t need) {
+    if (ctx->ws_thick_n >= need) return TR_OK;
+    hipFree(ctx->ws_thick);
+    ctx->ws_thick = nullptr;
+    ctx->ws_thick_n = 0;
+    if (hipMalloc(&ctx->ws_thick, sizeof(float4) * need) != hipSuccess)
+        return tr_fail(ctx, TR_ENOMEM, "thick-content accumulators (%lld bytes)", (long long)(sizeof(float4) * need));
+    k_zero_f32<<<(int)tr_div_up(4 * need, 256 * 64), 256, 0, ctx->stream>>>(reinterpret_cast<float *>(ctx->ws_thick),
+                                                                           4 * need);
+    ctx->ws_thick_n = need;
+    return TR_OK;
+}
+
+int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float *J, float *F,
+                 float *u_rad, int32_t *counters, bool count) {
+    if (!ctx) return TR_EINVAL;
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    Inst I;
+    int rc = setup_instance(ctx, t, p, J, F, u_rad, counters, count, I);
+    if (rc) return rc;
+    const int npix = I.npix;
+    const bool tab_lds = !count && npix <= 256;
+    const int lds_table = tab_lds ? table_bytes(I.M) : 0;
+    const int max_waves = max_waves_for(npix);
+    set_bp(I, choose_bp(I, p->bins_per_pass, lds_table, max_waves, count), count);
+    TraceArgs &A = I.A;
+    A.chunk = p->chunk > 0 ? p->chunk : 4;
     A.lds_table = lds_table;
     // waves per block: as many as fit in the CU's LDS together with the shared tables
-    int per_block = p->waves_per_block > 0 ? p->waves_per_block : (lds_cu - lds_table) / A.lds_wave;
+    int per_block = p->waves_per_block > 0 ? p->waves_per_block : (kLdsCu - lds_table) / A.lds_wave;
     if (per_block > max_waves) per_block = max_waves;
     if (per_block < 1) per_block = 1;
     A.per_block = per_block;
     const size_t lds = (size_t)lds_table + (size_t)per_block * A.lds_wave;
-    if (lds > (size_t)lds_cu) return tr_fail(ctx, TR_EINVAL, "LDS per block too large (%zu bytes)", lds);
+    if (lds > (size_t)kLdsCu) return tr_fail(ctx, TR_EINVAL, "LDS per block too large (%zu bytes)", lds);
     // one block per CU when the tables sit in LDS; otherwise as many blocks as fit
-    int blocks_cu = tab_lds ? 1 : (int)(lds_cu / lds);
+    int blocks_cu = tab_lds ? 1 : (int)(kLdsCu / lds);
     if (blocks_cu > 8) blocks_cu = 8;
     const int grid = ctx->n_cu * blocks_cu;
     A.thick = nullptr;
     if (!count) {
-        const int64_t need = (int64_t)grid * per_block * npix * bp;
-        if (ctx->ws_thick_n < need) {
-            hipFree(ctx->ws_thick);
-            ctx->ws_thick = nullptr;
-            ctx->ws_thick_n = 0;
-            if (hipMalloc(&ctx->ws_thick, sizeof(float4) * need) != hipSuccess)
-                return tr_fail(ctx, TR_ENOMEM, "thick-content accumulators (%lld bytes)",
-                               (long long)(sizeof(float4) * need));
-            k_zero_f32<<<(int)tr_div_up(4 * need, 256 * 64), 256, 0, ctx->stream>>>(
-                reinterpret_cast<float *>(ctx->ws_thick), 4 * need);
-            ctx->ws_thick_n = need;
-        }
+        rc = ensure_thick(ctx, (int64_t)grid * per_block * npix * A.bp);
+        if (rc) return rc;
         A.thick = ctx->ws_thick;
     }
     k_zero_int<<<1, 64, 0, ctx->stream>>>(ctx->d_ctl, 8);
@@ -804,9 +915,9 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
 #define LAUNCH(NS_, C_, T_) hipLaunchKernelGGL((k_trace<NS_, C_, T_>), dim3(grid), blk, lds, ctx->stream, A)
     if (count) {
         LAUNCH(1, true, false);
-    } else if (npix <= 64) {
+    } else if (nslot_for(npix) == 1) {
         LAUNCH(1, false, true);
-    } else if (npix <= 192) {
+    } else if (nslot_for(npix) == 3) {
         LAUNCH(3, false, true);
     } else {
         LAUNCH(12, false, false);
@@ -816,7 +927,376 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     return TR_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// Batched launches
+// ---------------------------------------------------------------------------------------
+struct Knobs {
+    int bp = 0, waves = 0, chunk = 0;
+};
+
 } // namespace
+
+struct tr_batch {
+    tr_ctx *ctx = nullptr;
+    std::vector<Inst> inst;
+    std::vector<int> start;   // prefix of target counts
+    TraceArgs *d_inst = nullptr;
+    int *d_start = nullptr;   // [2][n + 1]: all targets, then the tuner's sample
+    int sample_stride = 0;
+    std::vector<std::pair<int, int>> tabs; // (n_side, M) of each LDS table slot
+    int nslot = 1;
+    bool tab_lds = true;
+    int lds_table = 0;
+    Knobs knobs;
+    BatchArgs B{};
+    int grid = 0;
+    size_t lds = 0;
+    float4 *thick = nullptr;
+    int64_t thick_n = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float tuned_ms = 0.0f;
+};
+
+namespace {
+
+int batch_configure(tr_batch *b, Knobs k) {
+    tr_ctx *ctx = b->ctx;
+    int max_npix = 0;
+    for (auto &I : b->inst) max_npix = I.npix > max_npix ? I.npix : max_npix;
+    const int max_waves = max_waves_for(max_npix);
+    int lds_wave = 16, thick_wave = 0;
+    for (auto &I : b->inst) {
+        set_bp(I, choose_bp(I, k.bp, b->lds_table, max_waves, false), false);
+        lds_wave = I.A.lds_wave > lds_wave ? I.A.lds_wave : lds_wave;
+        thick_wave = I.npix * I.A.bp > thick_wave ? I.npix * I.A.bp : thick_wave;
+    }
+    int per_block = k.waves > 0 ? k.waves : (kLdsCu - b->lds_table) / lds_wave;
+    if (per_block > max_waves) per_block = max_waves;
+    if (per_block < 1) return tr_fail(ctx, TR_EINVAL, "batch: LDS too small for one wave (%d + %d bytes)",
+                                      b->lds_table, lds_wave);
+    const size_t lds = (size_t)b->lds_table + (size_t)per_block * lds_wave;
+    if (lds > (size_t)kLdsCu) return tr_fail(ctx, TR_EINVAL, "batch: LDS per block too large (%zu bytes)", lds);
+    int blocks_cu = b->tab_lds ? 1 : (int)(kLdsCu / lds);
+    if (blocks_cu > 8) blocks_cu = 8;
+    const int grid = ctx->n_cu * blocks_cu;
+    const int64_t need = (int64_t)grid * per_block * thick_wave;
+    if (b->thick_n < need) {
+        TR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        hipFree(b->thick);
+        b->thick = nullptr;
+        b->thick_n = 0;
+        if (hipMalloc(&b->thick, sizeof(float4) * need) != hipSuccess)
+            return tr_fail(ctx, TR_ENOMEM, "batch thick-content accumulators");
+        k_zero_f32<<<(int)tr_div_up(4 * need, 256 * 64), 256, 0, ctx->stream>>>(reinterpret_cast<float *>(b->thick),
+                                                                               4 * need);
+        b->thick_n = need;
+    }
+    std::vector<TraceArgs> h(b->inst.size());
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        h[i] = b->inst[i].A;
+        h[i].per_block = per_block;
+        h[i].thick = b->thick;
+        h[i].lds_table = b->lds_table;
+    }
+    TR_HIP(ctx, hipMemcpyAsync(b->d_inst, h.data(), sizeof(TraceArgs) * h.size(), hipMemcpyHostToDevice, ctx->stream));
+    TR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    BatchArgs &B = b->B;
+    B.inst = b->d_inst;
+    B.n_inst = (int)b->inst.size();
+    B.work = ctx->d_ctl;
+    B.chunk = k.chunk > 0 ? k.chunk : 4;
+    B.per_block = per_block;
+    B.lds_wave = lds_wave;
+    B.lds_table = b->lds_table;
+    B.thick = b->thick;
+    B.thick_wave = thick_wave;
+    b->knobs = k;
+    b->grid = grid;
+    b->lds = lds;
+    return TR_OK;
+}
+
+// one persistent launch on stream st over all targets (stride 1) or the tuner's sample
+int batch_enqueue(tr_batch *b, hipStream_t st, bool sample) {
+    BatchArgs B = b->B;
+    const int n = (int)b->inst.size();
+    B.start = b->d_start + (sample ? n + 1 : 0);
+    B.stride = sample ? b->sample_stride : 1;
+    if (sample) {
+        int tot = 0;
+        for (auto &I : b->inst) tot += (int)tr_div_up(I.A.n_targets, b->sample_stride);
+        B.n_total = tot;
+    } else {
+        B.n_total = b->start.back();
+    }
+    k_zero_int<<<1, 64, 0, st>>>(b->ctx->d_ctl, 8);
+    const dim3 blk(64 * B.per_block);
+#define LAUNCHB(NS_, T_) hipLaunchKernelGGL((k_trace_batch<NS_, T_>), dim3(b->grid), blk, b->lds, st, B)
+    if (b->nslot == 1) {
+        LAUNCHB(1, true);
+    } else if (b->nslot == 3) {
+        LAUNCHB(3, true);
+    } else {
+        LAUNCHB(12, false);
+    }
+#undef LAUNCHB
+    if (hipGetLastError() != hipSuccess) return tr_fail(b->ctx, TR_EHIP, "batched trace launch failed");
+    return TR_OK;
+}
+
+void batch_drop_graph(tr_batch *b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+int batch_capture(tr_batch *b) {
+    tr_ctx *ctx = b->ctx;
+    batch_drop_graph(b);
+    if (!b->cap) TR_HIP(ctx, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    TR_HIP(ctx, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = batch_enqueue(b, b->cap, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || !g) return tr_fail(ctx, TR_EHIP, "batch graph capture failed");
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        batch_drop_graph(b);
+        return tr_fail(ctx, TR_EHIP, "batch graph instantiation failed");
+    }
+    return TR_OK;
+}
+
+void batch_release(tr_batch *b) {
+    if (!b) return;
+    if (b->ctx) {
+        hipSetDevice(b->ctx->device);
+        hipStreamSynchronize(b->ctx->stream);
+    }
+    batch_drop_graph(b);
+    if (b->cap) hipStreamDestroy(b->cap);
+    hipFree(b->d_inst);
+    hipFree(b->d_start);
+    hipFree(b->thick);
+    delete b;
+}
+
+int batch_build(tr_ctx *ctx, int n, const tr_tree *const *trees, const tr_trace_params *p, float *const *J,
+                float *const *F, float *const *u_rad, tr_batch **out) {
+    if (!ctx) return TR_EINVAL;
+    if (!out || n < 1 || !trees || !p || !J || !F) return tr_fail(ctx, TR_EINVAL, "batch: bad argument");
+    *out = nullptr;
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    tr_batch *b = new tr_batch;
+    b->ctx = ctx;
+    b->inst.resize(n);
+    b->start.assign(n + 1, 0);
+    int64_t tot = 0;
+    int max_npix = 0;
+    for (int i = 0; i < n; ++i) {
+        int rc = setup_instance(ctx, trees[i], p + i, J[i], F[i], u_rad ? u_rad[i] : nullptr, nullptr, false,
+                                b->inst[i]);
+        if (rc) {
+            batch_release(b);
+            return rc;
+        }
+        Inst &I = b->inst[i];
+        tot += I.A.n_targets;
+        if (tot >= ((int64_t)1 << 31)) {
+            batch_release(b);
+            return tr_fail(ctx, TR_EINVAL, "batch: more than 2^31 targets");
+        }
+        b->start[i + 1] = (int)tot;
+        max_npix = I.npix > max_npix ? I.npix : max_npix;
+        const std::pair<int, int> key(I.npix, I.M);
+        int slot = -1;
+        for (size_t s = 0; s < b->tabs.size(); ++s)
+            if (b->tabs[s] == key) slot = (int)s;
+        if (slot < 0) {
+            if ((int)b->tabs.size() == kMaxTabs) {
+                batch_release(b);
+                return tr_fail(ctx, TR_EINVAL, "batch: more than %d distinct (N_side, cube_m)", kMaxTabs);
+            }
+            slot = (int)b->tabs.size();
+            b->tabs.push_back(key);
+            b->B.tab[slot] = I.rt->table;
+            b->B.sq[slot] = I.rt->square;
+            b->B.tab_ncell[slot] = 6 * I.M * I.M;
+        }
+        I.A.tab_slot = slot;
+    }
+    b->nslot = nslot_for(max_npix);
+    b->tab_lds = max_npix <= 256;
+    b->B.n_tab = (int)b->tabs.size();
+    int off = 0;
+    for (int s = 0; s < b->B.n_tab; ++s) {
+        b->B.tab_off[s] = off;
+        if (b->tab_lds) off += table_bytes(b->tabs[s].second);
+    }
+    b->lds_table = off;
+    if (hipMalloc(&b->d_inst, sizeof(TraceArgs) * n) != hipSuccess ||
+        hipMalloc(&b->d_start, sizeof(int) * 2 * (n + 1)) != hipSuccess) {
+        batch_release(b);
+        return tr_fail(ctx, TR_ENOMEM, "batch descriptors");
+    }
+    if (hipMemcpy(b->d_start, b->start.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        batch_release(b);
+        return tr_fail(ctx, TR_EHIP, "batch descriptor upload");
+    }
+    Knobs k;
+    k.bp = p[0].bins_per_pass;
+    k.waves = p[0].waves_per_block;
+    k.chunk = p[0].chunk;
+    int rc = batch_configure(b, k);
+    if (rc) {
+        batch_release(b);
+        return rc;
+    }
+    *out = b;
+    return TR_OK;
+}
+
+int batch_set_sample(tr_batch *b, int stride) {
+    if (stride < 1) stride = 1;
+    if (b->sample_stride == stride) return TR_OK;
+    const int n = (int)b->inst.size();
+    std::vector<int> st(n + 1, 0);
+    for (int i = 0; i < n; ++i) st[i + 1] = st[i] + (int)tr_div_up(b->inst[i].A.n_targets, stride);
+    TR_HIP(b->ctx, hipMemcpy(b->d_start + n + 1, st.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+    b->sample_stride = stride;
+    return TR_OK;
+}
+
+// time one configuration on the tuner's sample: best of `reps` launches, in ms
+int batch_time(tr_batch *b, Knobs k, int reps, float *ms) {
+    tr_ctx *ctx = b->ctx;
+    int rc = batch_configure(b, k);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    TR_HIP(ctx, hipEventCreate(&e0));
+    TR_HIP(ctx, hipEventCreate(&e1));
+    float best = 1e30f;
+    rc = batch_enqueue(b, ctx->stream, true); // warm-up
+    for (int r = 0; r < reps && rc == TR_OK; ++r) {
+        hipEventRecord(e0, ctx->stream);
+        rc = batch_enqueue(b, ctx->stream, true);
+        hipEventRecord(e1, ctx->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = tr_fail(ctx, TR_EHIP, "batch tuning: event wait failed");
+        float t = 0.0f;
+        hipEventElapsedTime(&t, e0, e1);
+        best = t < best ? t : best;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc == TR_OK && ctx->d_ctl) {
+        rc = tr_sync(ctx);
+    }
+    *ms = best;
+    return rc;
+}
+
+} // namespace
+
+extern "C" int tr_batch_create(tr_ctx *ctx, int n, const tr_tree *const *trees, const tr_trace_params *p,
+                               float *const *J, float *const *F, float *const *u_rad, tr_batch **out) {
+    int rc = batch_build(ctx, n, trees, p, J, F, u_rad, out);
+    if (rc) return rc;
+    rc = batch_capture(*out);
+    if (rc) {
+        batch_release(*out);
+        *out = nullptr;
+    }
+    return rc;
+}
+
+extern "C" int tr_batch_launch(tr_batch *b) {
+    if (!b) return TR_EINVAL;
+    TR_HIP(b->ctx, hipSetDevice(b->ctx->device));
+    if (!b->exec) return tr_fail(b->ctx, TR_EINVAL, "batch has no graph");
+    TR_HIP(b->ctx, hipGraphLaunch(b->exec, b->ctx->stream));
+    return TR_OK;
+}
+
+extern "C" int tr_batch_launch_eager(tr_batch *b) {
+    if (!b) return TR_EINVAL;
+    TR_HIP(b->ctx, hipSetDevice(b->ctx->device));
+    return batch_enqueue(b, b->ctx->stream, false);
+}
+
+extern "C" int tr_batch_tune(tr_batch *b, int sample_stride, tr_batch_tuning *best) {
+    if (!b) return TR_EINVAL;
+    tr_ctx *ctx = b->ctx;
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    int rc = batch_set_sample(b, sample_stride);
+    if (rc) return rc;
+    int max_bins = 1;
+    for (auto &I : b->inst) max_bins = I.A.n_bins > max_bins ? I.A.n_bins : max_bins;
+    // coordinate descent: segments per pass, then waves per block, then the queue chunk
+    Knobs cur;
+    cur.chunk = 4;
+    float cur_ms = 0.0f;
+    rc = batch_time(b, cur, 2, &cur_ms);
+    if (rc) return rc;
+    const int bps[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    for (int v : bps) {
+        if (v > max_bins) break;
+        Knobs k = cur;
+        k.bp = v;
+        float ms = 0.0f;
+        if (batch_time(b, k, 2, &ms) != TR_OK) continue; // does not fit: skip
+        if (ms < cur_ms) { cur = k; cur_ms = ms; }
+    }
+    const int waves[] = {4, 8, 12};
+    for (int v : waves) {
+        Knobs k = cur;
+        k.waves = v;
+        float ms = 0.0f;
+        if (batch_time(b, k, 2, &ms) != TR_OK) continue;
+        if (ms < cur_ms) { cur = k; cur_ms = ms; }
+    }
+    const int chunks[] = {1, 2, 8, 16, 32};
+    for (int v : chunks) {
+        Knobs k = cur;
+        k.chunk = v;
+        float ms = 0.0f;
+        if (batch_time(b, k, 2, &ms) != TR_OK) continue;
+        if (ms < cur_ms) { cur = k; cur_ms = ms; }
+    }
+    ctx->err.clear();
+    rc = batch_configure(b, cur);
+    if (rc) return rc;
+    b->tuned_ms = cur_ms;
+    rc = batch_capture(b);
+    if (rc) return rc;
+    if (best) {
+        int bp = 1;
+        for (auto &I : b->inst) bp = I.A.bp > bp ? I.A.bp : bp;
+        best->bins_per_pass = bp;
+        best->waves_per_block = b->B.per_block;
+        best->chunk = b->B.chunk;
+        best->sample_ms = cur_ms;
+    }
+    return TR_OK;
+}
+
+extern "C" void tr_batch_free(tr_batch *b) { batch_release(b); }
+
+extern "C" int tr_trace_rays_batched(tr_ctx *ctx, int n, const tr_tree *const *trees, const tr_trace_params *p,
+                                     float *const *J, float *const *F, float *const *u_rad) {
+    tr_batch *b = nullptr;
+    int rc = batch_build(ctx, n, trees, p, J, F, u_rad, &b);
+    if (rc) return rc;
+    rc = batch_enqueue(b, ctx->stream, false);
+    batch_release(b); // waits for the launch before the descriptors go
+    return rc;
+}
 
 extern "C" int tr_trace_rays(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float *J,
                              float *F, float *u_rad) {
