@@ -91,7 +91,7 @@ def train_network(T, ctx, name, steps):
     return mlp, losses
 
 
-def cpu_baseline(w, n_pix, stride, u_rad=None):
+def cpu_baseline(w, n_pix, stride, u_rad=None, gpu_t_dust=None):
     """FP64 oracle on the host cores: tree, every `stride`-th target, force and dust."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -103,15 +103,18 @@ def cpu_baseline(w, n_pix, stride, u_rad=None):
     J, F = ot.trace(oracle.params(w.n_side, theta=w.theta), cells=cells, n_threads=threads)
     t_trace = time.perf_counter() - t0
     t_dust = 0.0
+    errs = None
     if w.cgs and w.t_gas is not None:
         m = min(w.n_cells, 200_000)
         rho = w.rho[:m].astype(np.float64)
         u = np.full(m, 1e-10) if u_rad is None else np.asarray(u_rad[:m], np.float64)
         t0 = time.perf_counter()
-        oracle.dust_eq(rho, u, w.t_gas[:m].astype(np.float64), w.units[0], w.units[1], 3.8e-33)
+        To, _ = oracle.dust_eq(rho, u, w.t_gas[:m].astype(np.float64), w.units[0], w.units[1], 3.8e-33)
         t_dust = (time.perf_counter() - t0) * w.n_cells / m
+        if gpu_t_dust:
+            errs = {k: float(np.max(np.abs(v[:m] - To) / To)) for k, v in gpu_t_dust.items()}
     t_step = t_tree + t_trace * (w.n_cells / len(cells)) + t_dust
-    return {
+    out = {
         "value": w.n_cells * n_pix / t_step,
         "unit": "target-ray evaluations/s",
         "cores": threads,
@@ -121,6 +124,9 @@ def cpu_baseline(w, n_pix, stride, u_rad=None):
                    f"{w.n_cells} targets, dust equilibrium timed on {min(w.n_cells, 200_000)} cells "
                    f"and scaled; estimated step {t_step:.1f} s"),
     }
+    if errs:
+        out["dust_max_rel_err"] = errs
+    return out
 
 
 def _rocpd(paths):
@@ -346,37 +352,55 @@ def main():
             "walk_totals": {"b_nodes_accepted": int(c[0]), "h_nodes_accepted": int(c[1]),
                             "h_nodes_opened": int(c[2])}}
 
-    # dust: learned vs plain guess at the same stopping rule, judged by the plain solve
+    # dust: the learned start against the solve without the network, same stopping rule;
+    # "plain" is Newton on the residual from the bracket end nearer the root (bisection
+    # safeguarded); the log-space variants are this library's stronger analytic starts
     dust = None
+    dust_T = {}
     if w.cgs:
-        TP = torch.empty(n, device="cuda")
-        ITP = torch.empty(n, dtype=torch.uint8, device="cuda")
-        def timed(m, out, it, reps=20):
+        variants = {"learned": (mlp, {}),
+                    "plain": (None, dict(start=1, linear=True, max_iter=250)),
+                    "plain_log_newton": (None, dict(start=1)),
+                    "secant_log_newton": (None, dict(start=0))}
+        stats = {}
+        for name, (m, kw) in variants.items():
+            out = torch.empty(n, device="cuda")
+            it = torch.empty(n, dtype=torch.uint8, device="cuda")
+            dpv = T.dust_params(w.units[0], w.units[1], **kw)
+            T.dust_equilibrium(ctx, dev["rho"], U, dev["t_gas"], dpv, out, it, m)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            T.dust_equilibrium(ctx, dev["rho"], U, dev["t_gas"], dp, out, it, m)
+            reps = 20
             e0.record()
             for _ in range(reps):
-                T.dust_equilibrium(ctx, dev["rho"], U, dev["t_gas"], dp, out, it, m)
+                T.dust_equilibrium(ctx, dev["rho"], U, dev["t_gas"], dpv, out, it, m)
             e1.record()
             torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / reps
-        ms_plain = timed(None, TP, ITP)
-        ms_learned = timed(mlp, TD, IT)
-        err = (TD - TP).abs() / TP
+            ms_v = e0.elapsed_time(e1) / reps
+            itf = it.float()
+            stats[name] = {"ms": round(ms_v, 4), "solves_per_s": n / (ms_v / 1000.0),
+                           "mean_iters": round(float(itf.mean().item()), 3),
+                           "max_iters": int(it.max().item())}
+            dust_T[name] = out.cpu().numpy()
+        ref = dust_T["plain"]
+        for name in stats:
+            stats[name]["max_rel_diff_vs_plain"] = float(np.max(np.abs(dust_T[name] - ref) / ref))
+        best_analytic = min(stats[k]["ms"] for k in stats if k != "learned")
         dust = {"unit": "T_dust solves/s",
-                "learned_solves_per_s": n / (ms_learned / 1000.0),
-                "plain_solves_per_s": n / (ms_plain / 1000.0),
-                "speedup_learned_over_plain": round(ms_plain / ms_learned, 3),
-                "max_rel_diff_learned_vs_plain": float(err.max().item()),
-                "mean_newton_iters_learned": float(IT.float().mean().item()),
-                "mean_newton_iters_plain": float(ITP.float().mean().item()),
-                "stop_rule": "|dT| <= 1e-6 T or residual at rounding level, bracket-safeguarded",
+                "learned_solves_per_s": stats["learned"]["solves_per_s"],
+                "plain_solves_per_s": stats["plain"]["solves_per_s"],
+                "speedup_learned_over_plain": round(stats["plain"]["ms"] / stats["learned"]["ms"], 3),
+                "speedup_learned_over_best_analytic_start": round(best_analytic / stats["learned"]["ms"], 3),
+                "variants": stats,
+                "stop_rule": "|dT| <= 1e-6 T or bracket width <= 1e-6 T, bracket-safeguarded",
                 "network": train_info}
 
     base = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        base = cpu_baseline(w, n_pix, args.cpu_stride, U.cpu().numpy())
+        base = cpu_baseline(w, n_pix, args.cpu_stride, U.cpu().numpy(), dust_T)
+        if dust is not None and base.get("dust_max_rel_err"):
+            for k, v in base.pop("dust_max_rel_err").items():
+                dust["variants"][k]["max_rel_err_vs_oracle"] = v
 
     out = {
         "metric": "target-ray evaluations/s + T_dust solves/s, learned vs plain at fixed error",

@@ -178,11 +178,14 @@ typedef struct tr_dust_params {
     double xi;        /* factor on the radiative rates (1 = kappa per gram of gas) */
     float rel_tol;    /* Newton stop |dT| <= rel_tol T (0 selects 1e-6) */
     int32_t max_iter; /* 0 selects 50 */
+    int32_t start;    /* without a network: 0 = secant point of the bracket in (ln T, ln w),
+                         1 = the bracket end with the smaller |ln(w/K)| */
+    int32_t linear;   /* 0 = Newton on ln w(T) against ln T, 1 = Newton on the residual g(T) */
 } tr_dust_params;
 
 /* rho, u_rad, t_gas: device float[n]; t_dust: device float[n]; iters: device uint8[n]
- * or NULL (Newton/bisection steps taken).  mlp: trained guess network or NULL for the
- * plain start (the secant point of the bracket). */
+ * or NULL (Newton/bisection steps taken).  mlp: trained guess network (its output is the
+ * starting point) or NULL for the plain start chosen by p->start. */
 int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, const float *u_rad,
                         const float *t_gas, const tr_dust_params *p, const tr_mlp *mlp,
                         float *t_dust, uint8_t *iters);

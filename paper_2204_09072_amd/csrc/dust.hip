@@ -4,9 +4,9 @@
 //   g(T) = xi 4 sigma kappa(T) T^4 - xi 4 pi kappa(T_J) J - C (T_g - T),
 //   C    = c_gd rho / (1.4 m_H)^2 sqrt(T_g) (1 - 0.8 exp(-75 / T_g)),
 // is strictly increasing, negative at min(T_g, T_J) and positive at max(T_g, T_J).
-// Newton's method (on ln w against ln T, see the kernel) runs inside that bracket, with
-// bisection when a step leaves it; the starting point is the bracket's secant point in
-// logarithms, or the guess network's output.
+// Newton's method (by default on ln w against ln T, see the kernel) runs inside that
+// bracket, with bisection when a step leaves it; the starting point is the bracket's secant
+// point in logarithms, the bracket end nearer the root, or the guess network's output.
 #include "common.hpp"
 #include "mlp.hpp"
 
@@ -41,10 +41,16 @@ struct DustArgs {
     float cgd_n;    // c_gd / (1.4 m_H)^2
     float tol;
     int max_iter;
-    const float *guess; // learned starting points (NULL: plain start)
+    const float *guess; // learned starting points (START_LEARNED)
 };
 
-template <bool LEARNED>
+enum Start { START_SECANT = 0, START_END = 1, START_LEARNED = 2 };
+
+// START: where Newton begins (the bracket's secant point in logarithms, the bracket end
+// with the smaller |ln(w/K)|, or the guess network's output).  LOG: Newton on ln w against
+// ln T (else on g(T) itself).  Every variant keeps the bracket and bisects when a step
+// leaves it, and stops on the same rule.
+template <int START, bool LOG>
 __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= A.n) return;
@@ -54,9 +60,9 @@ __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
     const float H = A.xi4pi * kap_planck(tj) * J;
     const float C = A.cgd_n * rho * sqrtf(tg) * (1.0f - 0.8f * __expf(-75.0f / tg));
     // g(T) = w(T) - K with w = xi 4 sigma kappa(T) T^4 + C T increasing and convex and
-    // K = heating + C T_g.  Newton runs on ln w against ln T: for either dominant term
-    // (T^6 below 150 K, T^4 above, or T) ln w is nearly linear in ln T, so the iteration
-    // converges fast from both sides of the root.
+    // K = heating + C T_g.  In logarithms either dominant term (T^6 below 150 K, T^4
+    // above, or T) makes ln w nearly linear in ln T, so Newton there converges fast from
+    // both sides of the root.
     const float K = H + C * tg;
     auto wf = [&](float t, float &dw) {
         float v, dv;
@@ -72,26 +78,31 @@ __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
     } else {
         bool done = false;
         float wl = 0.0f;
-        if (!LEARNED || lo == kFloor) {
+        if (START != START_LEARNED || lo == kFloor) {
             wl = wf(lo, dw);
             if (wl >= K) { T = lo; done = true; } // root at or below the lower end (floor)
         }
         if (!done) {
-            if (LEARNED) {
+            if (START == START_LEARNED) {
                 T = A.guess[c];
                 if (!(T > lo)) T = lo;   // also catches NaN from a poisoned network
                 if (!(T < hi)) T = hi;
             } else {
-                // plain start: secant of the bracket in (ln T, ln w)
                 const float wh = wf(hi, dw);
-                const float ll = logf(lo), lh = logf(hi);
-                T = expf(ll + (logf(K) - logf(wl)) * (lh - ll) / (logf(wh) - logf(wl)));
-                if (!(T > lo && T < hi)) T = sqrtf(lo * hi);
+                const float rl = __logf(K) - __logf(wl), rh = __logf(wh) - __logf(K);
+                if (START == START_END) {
+                    T = rl < rh ? lo : hi;
+                } else {
+                    // secant of the bracket in (ln T, ln w)
+                    const float ll = __logf(lo), lh = __logf(hi);
+                    T = __expf(ll + rl * (lh - ll) / (rl + rh));
+                    if (!(T > lo && T < hi)) T = sqrtf(lo * hi);
+                }
             }
             for (it = 1; it <= A.max_iter; ++it) {
                 const float wv = wf(T, dw);
                 if (wv < K) lo = T; else hi = T;
-                float Tn = T * expf(-logf(wv / K) * wv / (T * dw));
+                float Tn = LOG ? T * __expf(-__logf(wv / K) * wv / (T * dw)) : T - (wv - K) / dw;
                 if (!(Tn > lo && Tn < hi)) Tn = 0.5f * (lo + hi);
                 const bool conv = fabsf(Tn - T) <= A.tol * Tn || hi - lo <= A.tol * hi;
                 T = Tn;
@@ -114,6 +125,8 @@ extern "C" int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, con
         return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad argument");
     if (!(p->sigma > 0) || !(p->c > 0) || p->c_gd < 0 || p->xi <= 0)
         return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad constants");
+    if (p->start < 0 || p->start > 1 || p->linear < 0 || p->linear > 1)
+        return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad start (%d) or linear (%d)", p->start, p->linear);
     if (n == 0) return TR_OK;
     TR_HIP(ctx, hipSetDevice(ctx->device));
     DustArgs A;
@@ -139,9 +152,14 @@ extern "C" int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, con
         int rc = mlp_guess(ctx, mlp, n, rho, u_rad, t_gas, ctx->ws_guess);
         if (rc) return rc;
         A.guess = ctx->ws_guess;
-        k_dust<true><<<blocks, 256, 0, ctx->stream>>>(A);
+        if (p->linear) k_dust<START_LEARNED, false><<<blocks, 256, 0, ctx->stream>>>(A);
+        else k_dust<START_LEARNED, true><<<blocks, 256, 0, ctx->stream>>>(A);
+    } else if (p->start == 1) {
+        if (p->linear) k_dust<START_END, false><<<blocks, 256, 0, ctx->stream>>>(A);
+        else k_dust<START_END, true><<<blocks, 256, 0, ctx->stream>>>(A);
     } else {
-        k_dust<false><<<blocks, 256, 0, ctx->stream>>>(A);
+        if (p->linear) k_dust<START_SECANT, false><<<blocks, 256, 0, ctx->stream>>>(A);
+        else k_dust<START_SECANT, true><<<blocks, 256, 0, ctx->stream>>>(A);
     }
     if (hipGetLastError() != hipSuccess) return tr_fail(ctx, TR_EHIP, "dust kernel launch failed");
     return TR_OK;

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
             const float wa = w1[3 * j], wb = w1[3 * j + 1], wc = w1[3 * j + 2], bj = b1[j];
             for (int s = 0; s < S; ++s) {
                 const float a = bj + wa * L.xs[s][0] + wb * L.xs[s][1] + wc * L.xs[s][2];
-                L.h1[s * LD + j] = bf16_bits(tanhf(a));
+                L.h1[s * LD + j] = bf16_bits(tanh_fast(a));
             }
         }
         __builtin_amdgcn_s_waitcnt(0xc07f);
@@ -150,27 +150,49 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
             const int n = 32 * tn + col;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                h2[tn][v] = tanhf(acc[tn][v] + b2[n]);
+                h2[tn][v] = tanh_fast(acc[tn][v] + b2[n]);
                 yp[v] += w3[n] * bf16_val(bf16_bits(h2[tn][v]));
             }
+        }
+        // rows held by this lane: s = 8 (v/4) + 4 half + v%4
+        if (MODE != TRAIN) {
+            // sum over the 32 lanes of a half-wave by halving exchanges: after the steps
+            // over lane bits 4, 3, 2, 1 (8 + 4 + 2 + 1 shuffles) and a last one over bit
+            // 0, lane l holds the full sum of row v = 8 b4 + 4 b3 + 2 b2 + b1, b_k being
+            // bit k of the lane
+            float r8[8], r4[4], r2[2], r1;
+            const bool k4 = col & 16, k3 = col & 8, k2 = col & 4, k1 = col & 2;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float keep = k4 ? yp[j + 8] : yp[j], send = k4 ? yp[j] : yp[j + 8];
+                r8[j] = keep + __shfl_xor(send, 16);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float keep = k3 ? r8[j + 4] : r8[j], send = k3 ? r8[j] : r8[j + 4];
+                r4[j] = keep + __shfl_xor(send, 8);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const float keep = k2 ? r4[j + 2] : r4[j], send = k2 ? r4[j] : r4[j + 2];
+                r2[j] = keep + __shfl_xor(send, 4);
+            }
+            {
+                const float keep = k1 ? r2[1] : r2[0], send = k1 ? r2[0] : r2[1];
+                r1 = keep + __shfl_xor(send, 2);
+            }
+            r1 += __shfl_xor(r1, 1);
+            const int v = (k4 ? 8 : 0) + (k3 ? 4 : 0) + (k2 ? 2 : 0) + (k1 ? 1 : 0);
+            const int s = 8 * (v >> 2) + 4 * half + (v & 3);
+            if ((col & 1) == 0 && s < cnt) {
+                const float yv = r1 + b3;
+                A.out[s0 + s] = MODE == GUESS ? exp10f(yv / A.out_scale + A.out_shift) : yv;
+            }
+            continue;
         }
 #pragma unroll
         for (int v = 0; v < 16; ++v)
             for (int o = 1; o < 32; o <<= 1) yp[v] += __shfl_xor(yp[v], o);
-        // rows held by this lane: s = 8 (v/4) + 4 half + v%4
-        if (MODE != TRAIN) {
-            if (col == 0) {
-#pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int s = 8 * (v >> 2) + 4 * half + (v & 3);
-                    if (s < cnt) {
-                        const float yv = yp[v] + b3;
-                        A.out[s0 + s] = MODE == GUESS ? exp10f(yv / A.out_scale + A.out_shift) : yv;
-                    }
-                }
-            }
-            continue;
-        }
         float dy[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -231,7 +253,7 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int s = 8 * (v >> 2) + 4 * half + (v & 3);
-                const float h = tanhf(bi + wa * L.xs[s][0] + wb * L.xs[s][1] + wc * L.xs[s][2]);
+                const float h = tanh_fast(bi + wa * L.xs[s][0] + wb * L.xs[s][1] + wc * L.xs[s][2]);
                 const float da1 = d[v] * (1.0f - h * h);
                 gb1[ti] += da1;
                 gw1[ti][0] += da1 * L.xs[s][0];
@@ -317,18 +339,6 @@ MlpArgs base_args(const tr_mlp *m, int64_t n) {
 }
 
 } // namespace
-
-MlpDevice mlp_device(const tr_mlp *m) {
-    MlpDevice d;
-    d.wq = m->wq;
-    for (int k = 0; k < 3; ++k) {
-        d.shift[k] = m->norm[k];
-        d.scale[k] = m->norm[3 + k];
-    }
-    d.out_shift = m->norm[6];
-    d.out_scale = m->norm[7];
-    return d;
-}
 
 int mlp_guess(tr_ctx *ctx, const tr_mlp *m, int64_t n, const float *rho, const float *u_rad,
               const float *t_gas, float *guess) {

@@ -20,41 +20,20 @@ struct tr_mlp {
     float norm[8] = {0, 0, 0, 1, 1, 1, 0, 1};
 };
 
-struct MlpDevice {
-    const float *wq;
-    float shift[3], scale[3], out_shift, out_scale;
-};
-
-MlpDevice mlp_device(const tr_mlp *m);
 // temperature guesses of the network for raw (rho, u_rad, T_gas) fields, on the matrix cores
 int mlp_guess(tr_ctx *ctx, const tr_mlp *m, int64_t n, const float *rho, const float *u_rad,
               const float *t_gas, float *guess);
+
+// tanh x = 1 - 2 / (e^{2x} + 1) from the hardware exponential and reciprocal (absolute
+// error ~1e-7, far below the bfloat16 rounding of the activations); e^{2x} overflowing to
+// infinity gives 1 and underflowing to 0 gives -1.
+__device__ __forceinline__ float tanh_fast(float x) {
+    const float e = __expf(2.0f * x);
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
 
 __device__ __forceinline__ float bf16_round(float x) {
     uint32_t u = __float_as_uint(x);
     if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
     return __uint_as_float(u & 0xffff0000u);
-}
-
-// One sample through the network with weights W (bfloat16 values) in shared memory;
-// layer inputs rounded to bfloat16, FP32 accumulation.
-__device__ __forceinline__ float mlp_forward_one(const float *W, float x0, float x1, float x2) {
-    x0 = bf16_round(x0);
-    x1 = bf16_round(x1);
-    x2 = bf16_round(x2);
-    float h1[MLP_H];
-#pragma unroll
-    for (int j = 0; j < MLP_H; ++j) {
-        float a = W[MLP_OFF_B1 + j] + W[3 * j] * x0 + W[3 * j + 1] * x1 + W[3 * j + 2] * x2;
-        h1[j] = bf16_round(tanhf(a));
-    }
-    float y = W[MLP_OFF_B3];
-    for (int j = 0; j < MLP_H; ++j) {
-        float a = W[MLP_OFF_B2 + j];
-        const float *w = W + MLP_OFF_W2 + MLP_H * j;
-#pragma unroll
-        for (int k = 0; k < MLP_H; ++k) a += w[k] * h1[k];
-        y += W[MLP_OFF_W3 + j] * bf16_round(tanhf(a));
-    }
-    return y;
 }

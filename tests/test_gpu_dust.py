@@ -1,0 +1,89 @@
+"""Dust equilibrium on the GPU: every starting rule and iteration form against the FP64
+bracketed root of the oracle (rel 1e-5), and what the trained guess network gains over
+the solve without it."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+from test_gpu_parity import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_09072_amd as T
+    return T
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("start,linear", [(0, False), (1, False), (0, True), (1, True)])
+def test_dust_every_start_parity(lib, ctx, start, linear):
+    import torch
+    from paper_2204_09072_amd.run import dust
+    s = W.dust_samples(100_000, seed=22).astype(np.float32).astype(np.float64)
+    say("dust start", start, "linear", linear)
+    dev = [torch.from_numpy(s[:, k].astype(np.float32)).cuda() for k in range(3)]
+    T, it = dust(ctx, *dev, W.SIGMA_SB, W.C_LIGHT, start=start, linear=linear, max_iter=250)
+    ctx.sync()
+    To, _ = oracle.dust_eq(s[:, 0], s[:, 1], s[:, 2], W.SIGMA_SB, W.C_LIGHT, 3.8e-33)
+    rel = np.abs(T.cpu().numpy() - To) / To
+    it = it.cpu().numpy()
+    say("  max rel %.2e, iterations mean %.2f max %d" % (rel.max(), it.mean(), it.max()))
+    assert rel.max() < 1e-5
+    assert it.max() < 250
+
+
+def _cloud(ctx, seed):
+    """u_rad of a 32^3 collapsing core from the GPU trace, with rho and T_gas."""
+    from paper_2204_09072_amd.run import trace, upload
+    w = W.c3_core128(n=32, seed=seed, n_side=2)
+    dev = upload(w)
+    tree, J, F, U = trace(ctx, w, dev)
+    ctx.sync()
+    tree.free()
+    return w, dev["rho"], U, dev["t_gas"]
+
+
+def test_learned_guess_gain(lib, ctx):
+    """Train the guess network on one realisation of the core (labels from the library's
+    own solve), use it on another: same T_dust as the FP64 oracle, fewer Newton steps
+    than plain Newton on the residual started at the bracket end nearer the root."""
+    import torch
+    from paper_2204_09072_amd.guess import train_guess
+    from paper_2204_09072_amd.run import dust
+    w1, r1, u1, t1 = _cloud(ctx, 1)
+    lab, _ = dust(ctx, r1, u1, t1, W.SIGMA_SB, W.C_LIGHT)
+    ctx.sync()
+    say("training on", r1.numel(), "cells")
+    mlp, losses = train_guess(ctx, r1.cpu().numpy(), u1.cpu().numpy(), t1.cpu().numpy(), lab.cpu().numpy(),
+                              steps=600, batch=4096, log_every=200)
+    say("losses", losses)
+    assert losses[-1][1] < 0.1 * losses[0][1]
+    w2, r2, u2, t2 = _cloud(ctx, 2)
+    To, _ = oracle.dust_eq(r2.cpu().numpy().astype(np.float64), u2.cpu().numpy().astype(np.float64),
+                           t2.cpu().numpy().astype(np.float64), W.SIGMA_SB, W.C_LIGHT, 3.8e-33)
+    res = {}
+    for name, kw in (("learned", dict(mlp=mlp)), ("end_linear", dict(start=1, linear=True, max_iter=250)),
+                     ("end_log", dict(start=1)), ("secant_log", dict(start=0))):
+        T, it = dust(ctx, r2, u2, t2, W.SIGMA_SB, W.C_LIGHT, **kw)
+        ctx.sync()
+        rel = np.abs(T.cpu().numpy() - To) / To
+        res[name] = float(it.float().mean().item())
+        say("  %-10s max rel %.2e  mean iterations %.3f" % (name, rel.max(), res[name]))
+        assert rel.max() < 1e-5, name
+    # the network's guess saves steps over the plain Newton start it replaces; the
+    # log-space starts of this library are reported beside it (they need fewer steps)
+    assert res["learned"] < res["end_linear"]
+    mlp.free()
