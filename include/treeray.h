@@ -110,8 +110,11 @@ typedef struct tr_trace_params {
     float j_bg;            /* background intensity entering at the ray ends */
     int32_t bins_per_pass; /* ray segments per walk pass (at most 16); 0 = automatic */
     int32_t chunk;         /* targets taken per work-queue grab; 0 = automatic */
-    int32_t waves_per_block; /* persistent waves per block (one target per wave); 0 = as
-                                many as the LDS holds */
+    int32_t waves_per_block; /* waves per block; 0 = automatic */
+    int32_t kernel;        /* 0 = automatic, 1 = one wave per target (segments processed in
+                              passes of bins_per_pass radial points), 2 = one block of waves
+                              per target (all segments in LDS, one walk; needs N_side <= 4 and
+                              an opening angle >= 1/8) */
 } tr_trace_params;
 
 /* Trace all cells of the tree: J (device float[n_cells], IRXE), F (device float[3][n],

@@ -49,7 +49,8 @@ class TreeInfo(C.Structure):
 class TraceParams(C.Structure):
     _fields_ = [("n_side", C.c_int32), ("theta_num", C.c_int32), ("theta_den", C.c_int32),
                 ("cube_m", C.c_int32), ("merge", C.c_int32), ("j_bg", C.c_float),
-                ("bins_per_pass", C.c_int32), ("chunk", C.c_int32), ("waves_per_block", C.c_int32)]
+                ("bins_per_pass", C.c_int32), ("chunk", C.c_int32), ("waves_per_block", C.c_int32),
+                ("kernel", C.c_int32)]
 
 
 class BatchTuning(C.Structure):
@@ -196,10 +197,11 @@ def tree_export(ctx: Context, tree: Tree):
 
 
 def trace_params(n_side, theta=None, cube_m=0, merge=True, j_bg=0.0, bins_per_pass=0, chunk=0,
-                 waves_per_block=0) -> TraceParams:
+                 waves_per_block=0, kernel=0) -> TraceParams:
+    """kernel: 0 automatic, 1 one wave per target, 2 one block per target."""
     th = (0, 0) if theta is None else theta
     return TraceParams(int(n_side), int(th[0]), int(th[1]), int(cube_m), int(bool(merge)),
-                       float(j_bg), int(bins_per_pass), int(chunk), int(waves_per_block))
+                       float(j_bg), int(bins_per_pass), int(chunk), int(waves_per_block), int(kernel))
 
 
 def trace_rays(ctx: Context, tree: Tree, p: TraceParams, J, F, u_rad=None):

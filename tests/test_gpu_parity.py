@@ -147,13 +147,17 @@ def _check_trace(J, F, Jo, Fo):
     assert (dF <= tolF + 1e-30).all(), f"F: worst {np.max(dF / (tolF + 1e-30)):.3e} x tolerance"
 
 
-@pytest.mark.parametrize("case,bpp", [("sphere16", 0), ("turb32", 0), ("turb32", 3), ("amr_small", 0),
-                                      ("amr_small", 2), ("padded40", 0), ("core32", 1)])
-def test_trace_parity_all_targets(lib, ctx, case, bpp):
+# kernel 1: one wave per target (segments in passes); kernel 2: one block per target
+@pytest.mark.parametrize("case,bpp,kernel", [
+    ("sphere16", 0, 1), ("turb32", 0, 1), ("turb32", 3, 1), ("amr_small", 0, 1), ("amr_small", 2, 1),
+    ("padded40", 0, 1), ("core32", 1, 1),
+    ("sphere16", 0, 2), ("turb32", 0, 2), ("turb32", 5, 2), ("amr_small", 0, 2), ("amr_small", 3, 2),
+    ("padded40", 0, 2), ("core32", 0, 2)])
+def test_trace_parity_all_targets(lib, ctx, case, bpp, kernel):
     from paper_2204_09072_amd.run import trace
     w = TREE_CASES[case]()
-    say("trace", case, "bins_per_pass", bpp)
-    tree, J, F, U = trace(ctx, w, bins_per_pass=bpp)
+    say("trace", case, "bins_per_pass", bpp, "kernel", kernel)
+    tree, J, F, U = trace(ctx, w, bins_per_pass=bpp, kernel=kernel)
     ctx.sync()
     ot = oracle.Tree(w)
     Jo, Fo = ot.trace(oracle.params(w.n_side, theta=w.theta))
@@ -173,12 +177,13 @@ def test_trace_parity_merge_off_and_background(lib, ctx):
     _check_trace(J.cpu().numpy(), F.cpu().numpy().T, Jo, Fo)
 
 
-@pytest.mark.parametrize("name,n_sample", [("turb64", 1500), ("core128", 160)])
-def test_trace_parity_full_size_sampled(lib, ctx, name, n_sample):
+@pytest.mark.parametrize("name,n_sample,kernel", [("turb64", 1500, 0), ("core128", 160, 0),
+                                                  ("core128", 80, 1)])
+def test_trace_parity_full_size_sampled(lib, ctx, name, n_sample, kernel):
     from paper_2204_09072_amd.run import trace
     w = W.CONFIGS[name]()
-    say("trace full size", name, w.n_cells)
-    tree, J, F, U = trace(ctx, w)
+    say("trace full size", name, w.n_cells, "kernel", kernel)
+    tree, J, F, U = trace(ctx, w, kernel=kernel)
     ctx.sync()
     rng = np.random.default_rng(11)
     cells = np.sort(rng.choice(w.n_cells, n_sample, replace=False))
