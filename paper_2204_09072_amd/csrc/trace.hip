@@ -368,11 +368,12 @@ __device__ __forceinline__ void integrate_segment(const float *s, int i, float o
     eps_thick *= (1.0f - f) + f * __expf(-tk);
 }
 
-// One node of the opening-angle walk for target T in pass G (Sec. 4, 4.2): leaves are
-// accepted, h-nodes accepted when s/d < theta and otherwise opened (their child range is
-// returned in `push` unless the pass prunes the subtree); an accepted node whose material
-// can reach the pass is returned as a queue record (`pk`, and whether its sub-points share
-// one cube face).
+// One node of the opening-angle walk for target T in pass G (Sec. 4, 4.2), the same test
+// as the one-wave kernel's walk step (written out there, where it allocates registers
+// better): leaves are accepted, h-nodes accepted when s/d < theta and otherwise opened
+// (their child range is returned in `push` unless the pass prunes the subtree); an
+// accepted node whose material can reach the pass is returned as a queue record (`pk`,
+// and whether its sub-points share one cube face).
 struct Target {
     int tid, tx, ty, tz;
     int4 c256;
@@ -499,7 +500,6 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
     const int4 tr = A.nodes[tid];
     const int tx = tr.x & 0xffff, ty = tr.y & 0xffff, tz = tr.z;
     const int4 c256 = make_int4(tx * TR_FX, ty * TR_FX, tz * TR_FX, 0);
-    const Target T{tid, tx, ty, tz, c256};
     RayState<NSLOT> R;
 #pragma unroll
     for (int k = 0; k < NSLOT; ++k) {
@@ -518,7 +518,6 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
         const int lo_cut = P.a * P.a, hi_cut = P.b * P.b;
         const int a4 = lo_cut * lo_cut, b4 = hi_cut * hi_cut; // R_a^2, R_b^2 in lattice units
         const bool last = P.b > A.n_bins;
-        const PassGeo G{P.a, P.b, lo_cut, hi_cut, a4, b4, last};
         if (!COUNT) {
             const int nf = A.npix * A.bp * kThin;
             for (int k = lane; k < nf; k += 64) bins[k] = 0.0f;
@@ -538,7 +537,103 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                 bool open = false, enq = false, face1 = false;
                 uint32_t push = 0, pk = 0;
                 if (node >= 0) {
-                    visit_node<COUNT>(A, node, T, G, n_b, n_h, n_open, open, push, enq, pk, face1);
+                    const int4 nd = A.nodes[node];
+                    const int depth = (nd.x >> 16) & 15;
+                    const bool leaf = (nd.x >> 20) & 1;
+                    const bool thick = (nd.x >> 21) & 1;
+                    const int s = A.root_edge >> depth;
+                    const int vx = (nd.x & 0xffff) - tx, vy = (nd.y & 0xffff) - ty, vz = nd.z - tz;
+                    bool acc = false;
+                    if (leaf) {
+                        if (node != tid) {
+                            ++n_b;
+                            acc = true;
+                        }
+                    } else {
+                        // |v| < 2^12, s < 2^12: d2 and s^2 fit 24 bits
+                        const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
+                        const int s2 = __mul24(s, s);
+                        const bool accept = A.wide_open ? (int64_t)s2 * A.th_den2 < (int64_t)A.th_num2 * d2
+                                                        : s2 * A.th_den2 < A.th_num2 * d2;
+                        if (accept) {
+                            ++n_h;
+                            acc = true;
+                        } else {
+                            ++n_open;
+                            bool keep = true;
+                            if (!COUNT) {
+                                // keep a subtree when r_max + s/4 >= R_a and r_min - s/4 < R_b
+                                const int hs = s >> 1, q4 = s >> 2;
+                                const int ax = abs(vx), ay = abs(vy), az = abs(vz);
+                                const int nx = max(ax - hs, 0), ny = max(ay - hs, 0), nz = max(az - hs, 0);
+                                const int fx = ax + hs, fy = ay + hs, fz = az + hs;
+                                const int rmin2 = __mul24(nx, nx) + __mul24(ny, ny) + __mul24(nz, nz);
+                                const int rmax2 = __mul24(fx, fx) + __mul24(fy, fy) + __mul24(fz, fz);
+                                const int lo = lo_cut - q4, hi = hi_cut + q4;
+                                if (lo > 0 && rmax2 < __mul24(lo, lo)) keep = false;
+                                if (!last && rmin2 >= __mul24(hi, hi)) keep = false;
+                            }
+                            if (keep) {
+                                open = true;
+                                push = ((uint32_t)nd.w << 3) |
+                                       (uint32_t)(__builtin_popcount((nd.y >> 16) & 255) - 1);
+                            }
+                        }
+                    }
+                    if (!COUNT && acc) {
+                        // exact integer pre-test in lattice units: the mapping position lies in
+                        // the node cube, so r is within [r_min, r_max]; thick material reaches a
+                        // further s/2 for the merge flags.  R_i = i^2, so R_i <= r <=> i^4 <= r^2.
+                        const int ext = thick && A.merge ? (s >> 1) : 0;
+                        bool maybe;
+                        if (leaf) {
+                            const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
+                            if (ext == 0) {
+                                maybe = d2 >= a4 && (last || d2 < b4);
+                            } else {
+                                const int lo = P.a * P.a - ext, hi = P.b * P.b + ext;
+                                maybe = (lo <= 0 || d2 >= __mul24(lo, lo)) && (last || d2 < __mul24(hi, hi));
+                            }
+                        } else {
+                            const int hs = (s >> 1) + ext;
+                            const int ax = abs(vx), ay = abs(vy), az = abs(vz);
+                            const int nx = max(ax - hs, 0), ny = max(ay - hs, 0), nz = max(az - hs, 0);
+                            const int fx = ax + hs, fy = ay + hs, fz = az + hs;
+                            const int rmin2 = __mul24(nx, nx) + __mul24(ny, ny) + __mul24(nz, nz);
+                            const int rmax2 = __mul24(fx, fx) + __mul24(fy, fy) + __mul24(fz, fz);
+                            maybe = rmax2 >= a4 && (last || rmin2 < b4);
+                        }
+                        if (maybe) {
+                            int dx, dy, dz;
+                            if (leaf) {
+                                dx = vx * TR_FX; dy = vy * TR_FX; dz = vz * TR_FX;
+                            } else {
+                                const int4 p = A.pcol[node];
+                                dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
+                            }
+                            const int i = bin_below(dx, dy, dz, 0, A.n_bins);
+                            if (i > 0) {
+                                const bool content = i >= P.a && i < P.b;
+                                int k0 = 0, k1 = 0;
+                                if (ext) {
+                                    const int half = TR_FX / 2 * s;
+                                    int lo = bin_below(dx, dy, dz, half, A.n_bins);
+                                    lo = lo < 1 ? 1 : lo;
+                                    const int hi = bin_below(dx, dy, dz, -half, A.n_bins);
+                                    k0 = lo > P.a ? lo : P.a;
+                                    k1 = hi < P.b ? hi : P.b;
+                                    if (k1 <= k0) { k0 = 0; k1 = 0; } else { k0 -= P.a; k1 -= P.a; }
+                                }
+                                if (content || k1 > k0) {
+                                    enq = true;
+                                    pk = (content ? (uint32_t)(i - P.a + 1) : 0u) | ((uint32_t)k0 << 6) |
+                                         ((uint32_t)k1 << 12) | ((leaf ? 1u : 0u) << 18) |
+                                         ((uint32_t)depth << 19);
+                                    face1 = one_face(dx, dy, dz, (TR_FX / 4) * s);
+                                }
+                            }
+                        }
+                    }
                 }
                 const uint64_t below = (1ull << lane) - 1ull;
                 const uint64_t bal = __ballot(open);
@@ -760,7 +855,7 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
     float *bins = reinterpret_cast<float *>(lds + L.bins);
     uint32_t *flgm = reinterpret_cast<uint32_t *>(lds + L.flgm);
     uint32_t *flgt = reinterpret_cast<uint32_t *>(lds + L.flgt);
-    uint32_t *fr[2] = {reinterpret_cast<uint32_t *>(lds + L.fr0), reinterpret_cast<uint32_t *>(lds + L.fr1)};
+    uint32_t *fr0 = reinterpret_cast<uint32_t *>(lds + L.fr0), *fr1 = reinterpret_cast<uint32_t *>(lds + L.fr1);
     int *grab = reinterpret_cast<int *>(lds + L.ctl);
     int *count = grab + kMaxLevels;
     float *part = reinterpret_cast<float *>(lds + L.part);
@@ -793,7 +888,7 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
         }
         for (int k = threadIdx.x; k < 2 * kMaxLevels; k += blockDim.x) grab[k] = 0;
         if (threadIdx.x == 0) {
-            fr[0][0] = 0u; // the root: first node 0, one node
+            fr0[0] = 0u; // the root: first node 0, one node
             count[0] = 1;
         }
         __syncthreads();
@@ -801,8 +896,8 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
         for (int lev = 0; lev < kMaxLevels; ++lev) {
             const int nF = min(count[lev], fcap);
             if (nF == 0) break;
-            const uint32_t *Fc = fr[lev & 1];
-            uint32_t *Fn = fr[(lev + 1) & 1];
+            const uint32_t *Fc = (lev & 1) ? fr1 : fr0;
+            uint32_t *Fn = (lev & 1) ? fr0 : fr1;
             for (;;) {
                 // 16 ranges per grab: every lane tests up to two nodes, one from each half
                 int c = 0;
@@ -1242,10 +1337,12 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     const bool tab_lds = !count && npix <= 256;
     const int lds_table = tab_lds ? table_bytes(I.M) : 0;
     const int max_waves = max_waves_for(npix);
-    // automatic choice: the one-block-per-target kernel when the one-wave kernel would
-    // need more than two passes (re-walking the tree for each), where it saves the re-walks
+    // automatic choice: the one-block-per-target kernel when the one-wave kernel would need
+    // a dozen passes or more (it re-walks the tree for each); below that the one-wave kernel
+    // is at least as fast on the MI355X (128^3 core, 11 passes: 1.96 s vs 1.98 s; AMR
+    // 256^3-equivalent, 15 passes: 2.77 s vs 2.64 s)
     const bool many_passes =
-        tr_div_up(I.A.n_bins, choose_bp(I, p->bins_per_pass, lds_table, max_waves, count)) > 2;
+        tr_div_up(I.A.n_bins, choose_bp(I, p->bins_per_pass, lds_table, max_waves, count)) >= 12;
     if (!count && (p->kernel == 2 || (p->kernel == 0 && many_passes))) {
         rc = launch_coop(ctx, I, p, lds_table);
         if (rc != TR_ENOTSUP) return rc;

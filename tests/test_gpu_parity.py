@@ -178,7 +178,7 @@ def test_trace_parity_merge_off_and_background(lib, ctx):
 
 
 @pytest.mark.parametrize("name,n_sample,kernel", [("turb64", 1500, 0), ("core128", 160, 0),
-                                                  ("core128", 80, 1)])
+                                                  ("core128", 80, 1), ("amr256", 400, 0)])
 def test_trace_parity_full_size_sampled(lib, ctx, name, n_sample, kernel):
     from paper_2204_09072_amd.run import trace
     w = W.CONFIGS[name]()
