@@ -219,6 +219,60 @@ def traffic_probe(name):
     log(f"traffic probe {name}: one trace launch done")
 
 
+def ray_count_study(name):
+    """Cost and accuracy of 48, 192 and 768 rays on one workload (the paper's Sec. 7.6
+    comparison): trace time per N_side (opening angle 1/(2 N_side)), cost relative to 48
+    rays, and the radiation temperature T_J = (pi J / sigma)^(1/4) against 768 rays over
+    the whole domain and over its central half."""
+    import torch
+    import paper_2204_09072_amd as T
+    from paper_2204_09072_amd.run import params_of, upload
+    import workloads as W
+    w = make_workload(name)
+    ctx = T.Context(0)
+    dev = upload(w)
+    tree = T.build_tree(ctx, w.nb, w.max_level, w.blocks, w.x0, w.box_len, dev["rho"], dev["kappa"],
+                        dev["t_dust"], w.stars, w.units[0], w.units[1])
+    n = w.n_cells
+    J = torch.empty(n, device="cuda")
+    F = torch.empty((3, n), device="cuda")
+    res, tj = {}, {}
+    for ns in (2, 4, 8):
+        w.n_side, w.theta = ns, (1, 2 * ns)
+        p = params_of(w)
+        T.trace_rays(ctx, tree, p, J, F, None)   # warm-up (builds the ray tables)
+        ctx.sync()
+        best = 1e30
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            T.trace_rays(ctx, tree, p, J, F, None)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        ctx.sync()
+        tj[ns] = (np.pi * np.maximum(J.cpu().numpy().astype(np.float64), 0) / w.units[0]) ** 0.25
+        res[ns] = {"rays": 12 * ns * ns, "trace_ms": round(best, 3),
+                   "target_rays_per_s": n * 12 * ns * ns / (best / 1000.0)}
+        log(f"ray study {name}: N_side {ns}: {best:.1f} ms")
+    x = W.synth.cell_centres(w)
+    c = np.asarray(w.x0) + 0.5 * w.box_len
+    half = np.all(np.abs(x - c) < 0.25 * w.box_len, axis=1)
+    for ns in (2, 4):
+        r = tj[ns] / np.maximum(tj[8], 1e-300) - 1.0
+        res[ns]["t_j_residual_vs_768_full"] = {"mean": float(r.mean()), "std": float(r.std())}
+        res[ns]["t_j_residual_vs_768_half"] = {"mean": float(r[half].mean()), "std": float(r[half].std())}
+    base = res[2]["trace_ms"]
+    out = {"study": "ray count", "workload": f"{name}: {WORKLOADS[name]}", "n_cells": n,
+           "cost_ratio_48_192_768": [round(res[k]["trace_ms"] / base, 3) for k in (2, 4, 8)],
+           "paper_cost_ratio_48_192_768": [1.0, 4.39, 15.98],
+           "paper_t_j_residual_vs_768_half": {"48": "-15.4% +- 14%", "192": "-3.77% +- 5.31%"},
+           "paper_t_j_residual_vs_768_full": {"48": "-31.0% +- 17.9%", "192": "-13.2% +- 10.5%"},
+           "by_n_side": res}
+    print(json.dumps(out), flush=True)
+    tree.free()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +292,8 @@ def main():
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/trace_<workload>_traffic.json from two --pmc runs")
     ap.add_argument("--traffic-out", nargs="*", default=None)
+    ap.add_argument("--ray-study", action="store_true",
+                    help="trace cost and T_J accuracy at 48, 192 and 768 rays (prints one JSON line)")
     args = ap.parse_args()
     if args.summarize:
         print(summarize_kernels(args.summarize))
@@ -254,6 +310,9 @@ def main():
 
     if args.traffic_probe:
         traffic_probe(args.workload)
+        return
+    if args.ray_study:
+        ray_count_study(args.workload)
         return
 
     import torch

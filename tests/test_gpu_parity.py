@@ -192,6 +192,20 @@ def test_trace_parity_full_size_sampled(lib, ctx, name, n_sample, kernel):
     _check_trace(J.cpu().numpy()[cells], F.cpu().numpy().T[cells], Jo, Fo)
 
 
+def test_trace_parity_nside8_sampled(lib, ctx):
+    """768 rays (N_side = 8, opening angle 1/16): the wide-ray kernel (12 rays per lane,
+    direction tables in global memory) on a 32^3 turbulent box with a star."""
+    from paper_2204_09072_amd.run import trace
+    w = W.c2_turb64(n=32, n_side=8)
+    say("trace n_side 8", w.n_cells)
+    tree, J, F, U = trace(ctx, w)
+    ctx.sync()
+    cells = np.sort(np.random.default_rng(12).choice(w.n_cells, 400, replace=False))
+    ot = oracle.Tree(w)
+    Jo, Fo = ot.trace(oracle.params(8, theta=w.theta), cells=cells)
+    _check_trace(J.cpu().numpy()[cells], F.cpu().numpy().T[cells], Jo, Fo)
+
+
 def test_rad_force_parity(lib, ctx):
     from paper_2204_09072_amd.run import force, trace
     w = TREE_CASES["padded40"]()
