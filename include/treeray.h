@@ -115,6 +115,12 @@ typedef struct tr_trace_params {
                               passes of bins_per_pass radial points), 2 = one block of waves
                               per target (all segments in LDS, one walk; needs N_side <= 4 and
                               an opening angle >= 1/8) */
+    int32_t orientation;   /* orientation of the ray set (Sec. 7.6): 0 = HEALPix axes, 1..47 =
+                              a signed permutation of the axes applied to every target (axis
+                              permutation o / 8 in the order 012 021 102 120 201 210, sign
+                              flip of axis a for bit a of o % 8), -1 = one drawn per target
+                              cell from SplitMix64(orient_seed * 2^32 + cell) mod 48 */
+    uint32_t orient_seed;
 } tr_trace_params;
 
 /* Trace all cells of the tree: J (device float[n_cells], IRXE), F (device float[3][n],
@@ -192,6 +198,19 @@ typedef struct tr_dust_params {
 int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, const float *u_rad,
                         const float *t_gas, const tr_dust_params *p, const tr_mlp *mlp,
                         float *t_dust, uint8_t *iters);
+
+/* Self-consistent dust temperature (Sec. 2, 4.1, 4.6): repeat tree build (Planck-mean
+ * opacity and emission of the current T_dust; no kappa array), ray tracing and dust
+ * equilibrium until the largest relative change of T_dust is <= tol or max_iter sweeps.
+ * t_dust: device float[n], the starting temperature on entry and the result on return;
+ * J, F, u_rad: device outputs of the last trace (as tr_trace_rays).  *iterations and
+ * *max_rel_change (host, may be NULL) receive the sweeps done and the last change.
+ * Synchronous (one readback per sweep). */
+int tr_dust_fixed_point(tr_ctx *ctx, const tr_grid *grid, const float *rho, const float *t_gas,
+                        const tr_star *stars, int n_stars, const tr_units *units,
+                        const tr_trace_params *tp, const tr_dust_params *dp, const tr_mlp *mlp,
+                        int max_iter, float tol, float *t_dust, float *J, float *F, float *u_rad,
+                        int32_t *iterations, float *max_rel_change);
 
 /* Guess network for the dust equilibrium: inputs (log10 rho, log10 u_rad, log10 T_gas)
  * normalised as (v - shift) * scale, output log10 T_d = y / out_scale + out_shift;

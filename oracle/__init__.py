@@ -75,14 +75,16 @@ def _p(a):
 
 class _Params(C.Structure):
     _fields_ = [("n_side", C.c_int), ("theta_num", C.c_int), ("theta_den", C.c_int),
-                ("cube_m", C.c_int), ("merge", C.c_int), ("j_bg", C.c_double)]
+                ("cube_m", C.c_int), ("merge", C.c_int), ("j_bg", C.c_double),
+                ("orient", C.c_int), ("orient_seed", C.c_uint)]
 
 
-def params(n_side, theta=None, cube_m=None, merge=True, j_bg=0.0):
+def params(n_side, theta=None, cube_m=None, merge=True, j_bg=0.0, orient=0, orient_seed=0):
+    """orient: 0..47 signed axis permutation of the ray set, -1 drawn per target cell."""
     theta = (1, 2 * n_side) if theta is None else theta
     cube_m = DEFAULT_CUBE_PER_NSIDE * n_side if cube_m is None else cube_m
     return _Params(int(n_side), int(theta[0]), int(theta[1]), int(cube_m), int(bool(merge)),
-                   float(j_bg))
+                   float(j_bg), int(orient), int(orient_seed))
 
 
 class Tree:
@@ -228,3 +230,32 @@ def mlp(H, params_, x, y=None, round_bf16=False, grad=True):
     g = np.zeros(mlp_n_params(H)) if (grad and y is not None) else None
     loss = lib().or_mlp(int(H), _p(prm), n, _p(x), _p(yy), int(bool(round_bf16)), _p(out), _p(g))
     return loss, out, g
+
+
+def dust_fixed_point(w, n_iter, c_gd=3.8e-33, xi=1.0, tol=0.0, prm=None):
+    """Self-consistent dust temperature (Sec. 2, 4.1, 4.6): the dust temperature gives each
+    cell its Planck-mean opacity and emission, the traced field gives the dust temperature
+    through the equilibrium; repeated from w.t_dust for n_iter sweeps or until the largest
+    relative change is <= tol.  The tree reads the temperature in single precision, as the
+    cell arrays are stored.  Returns (T_dust, J, F, changes)."""
+    import copy
+    sigma, c = w.units
+    prm = params(w.n_side, theta=w.theta) if prm is None else prm
+    T = np.asarray(w.t_dust, np.float64)
+    rho = np.asarray(w.rho, np.float64)
+    tg = np.asarray(w.t_gas, np.float64)
+    changes = []
+    J = F = None
+    for _ in range(n_iter):
+        wk = copy.copy(w)
+        wk.kappa = None
+        wk.t_dust = T.astype(np.float32)
+        tree = Tree(wk)
+        J, F = tree.trace(prm)
+        Tn, _ = dust_eq(rho, 4.0 * np.pi * J / c, tg, sigma, c, c_gd, xi)
+        ch = float(np.max(np.abs(Tn - T) / Tn))
+        changes.append(ch)
+        T = Tn
+        if ch <= tol:
+            break
+    return T, J, F, changes

@@ -54,6 +54,9 @@ typedef struct {
     int cube_m;                 /* direction cells per cube-face edge */
     int merge;                  /* merge segments spanned by thick material */
     double j_bg;                /* background intensity at the ray ends */
+    int orient;                 /* ray-set orientation: 0..47 (signed axis permutation
+                                   applied to node offsets), -1 = drawn per target cell */
+    unsigned int orient_seed;   /* seed of the per-target draw */
 } or_params;
 
 /* Trace every target in `cells` (cell indices; NULL = all n cells, in cell order).

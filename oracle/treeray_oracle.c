@@ -519,6 +519,7 @@ typedef struct {
     int npix, nbins;
     int64_t c[3], c256[3];
     int64_t target;
+    int perm[3], sgn[3]; /* orientation of the ray set for this target */
     double *bins;    /* [npix][nbins+1][6] */
     uint8_t *flags;  /* [npix][nbins+1]: merge segment i with i+1 */
     int64_t n_b, n_h, n_open;
@@ -538,11 +539,13 @@ static int bin_below(int64_t r2, int64_t off, int nbins) {
 
 static void map_node(walk_ctx *w, int64_t id) {
     const or_tree *t = w->t;
-    int64_t dl[3], r2 = 0;
+    int64_t d0[3], dl[3], r2 = 0;
     for (int a = 0; a < 3; ++a) {
-        dl[a] = t->p[3 * id + a] - w->c256[a];
-        r2 += dl[a] * dl[a];
+        d0[a] = t->p[3 * id + a] - w->c256[a];
+        r2 += d0[a] * d0[a];
     }
+    /* the node offset in the frame of the (re-oriented) ray set */
+    for (int a = 0; a < 3; ++a) dl[a] = w->sgn[a] * d0[w->perm[a]];
     int i = bin_below(r2, 0, w->nbins);
     if (i == 0) return; /* the target's own segment carries nothing (tau_0 = 0) */
     /* radial kernel: beta = R_i^2 / r^2 keeps inverse-square quantities conserved */
@@ -662,6 +665,29 @@ double or_integrate_ray(int ns, int nbins, const double *bins, const uint8_t *fl
     return Fh;
 }
 
+/* Orientation of the ray set (Sec. 7.6 names different HEALPix orientations as the remedy for
+ * ray artefacts): one of the 48 signed permutations of the axes, which
+ * map the integer lattice onto itself.  Index o: axis permutation o / 8 (in the order
+ * 012 021 102 120 201 210), sign flip of axis a when bit a of o % 8 is set; a node offset
+ * d becomes (s_0 d[p_0], s_1 d[p_1], s_2 d[p_2]).  A per-target draw uses the SplitMix64
+ * generator (Steele, Lea and Flood 2014) of seed * 2^32 + cell. */
+static uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+static void orientation(const or_params *p, int64_t cell, int *perm, int *sgn) {
+    static const int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int o = p->orient;
+    if (o < 0) o = (int)(splitmix64(((uint64_t)p->orient_seed << 32) | (uint64_t)(uint32_t)cell) % 48u);
+    for (int a = 0; a < 3; ++a) {
+        perm[a] = P[o >> 3][a];
+        sgn[a] = ((o >> a) & 1) ? -1 : 1;
+    }
+}
+
 static int trace_target(const or_tree *t, const or_params *p, const int32_t *table,
                         const double *dirs, int64_t cell, int brute, double *bins,
                         uint8_t *flags, double *Fh_out, double *tau_out, double *J,
@@ -673,6 +699,7 @@ static int trace_target(const or_tree *t, const or_params *p, const int32_t *tab
     memset(&w, 0, sizeof(w));
     w.t = t; w.p = p; w.table = table; w.npix = npix; w.nbins = nbins;
     w.target = t->node_of_cell[cell];
+    orientation(p, cell, w.perm, w.sgn);
     for (int a = 0; a < 3; ++a) {
         w.c[a] = t->g[3 * w.target + a];
         w.c256[a] = w.c[a] * FX;
@@ -710,7 +737,8 @@ static int trace_target(const or_tree *t, const or_params *p, const int32_t *tab
         Jsrc = -expm1(-0.5 * t->tau[tn]) * t->Lsrc[tn] / (4.0 * M_PI * (e * e));
     }
     if (J) *J = Js / (4.0 * M_PI) + Jsrc;
-    if (F) for (int a = 0; a < 3; ++a) F[a] = Fv[a];
+    /* Fv is in the ray set's frame: back to the grid's axes */
+    if (F) for (int a = 0; a < 3; ++a) F[w.perm[a]] = w.sgn[a] * Fv[a];
     if (counters) { counters[0] = w.n_b; counters[1] = w.n_h; counters[2] = w.n_open; }
     return 0;
 }
@@ -719,6 +747,7 @@ static int check_params(const or_tree *t, const or_params *p) {
     if (!t || !p) return -1;
     if (p->n_side < 1 || p->n_side > 64 || (p->n_side & (p->n_side - 1))) return -1;
     if (p->theta_num < 0 || p->theta_den <= 0 || p->cube_m < 1) return -1;
+    if (p->orient < -1 || p->orient > 47) return -1;
     return 0;
 }
 

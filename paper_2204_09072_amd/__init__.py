@@ -50,7 +50,7 @@ class TraceParams(C.Structure):
     _fields_ = [("n_side", C.c_int32), ("theta_num", C.c_int32), ("theta_den", C.c_int32),
                 ("cube_m", C.c_int32), ("merge", C.c_int32), ("j_bg", C.c_float),
                 ("bins_per_pass", C.c_int32), ("chunk", C.c_int32), ("waves_per_block", C.c_int32),
-                ("kernel", C.c_int32)]
+                ("kernel", C.c_int32), ("orientation", C.c_int32), ("orient_seed", C.c_uint32)]
 
 
 class BatchTuning(C.Structure):
@@ -90,6 +90,9 @@ _sig("tr_batch_free", None, [_P])
 _sig("tr_trace_rays_batched", _I, [_P, _I, _P, _P, _P, _P, _P])
 _sig("tr_ray_tables", _I, [_P, _I, _I, _P, _P])
 _sig("tr_rad_force", _I, [_P, _P, _P, _P, _P])
+_sig("tr_dust_fixed_point", _I, [_P, C.POINTER(Grid), _P, _P, _P, _I, C.POINTER(Units), C.POINTER(TraceParams),
+                                  C.POINTER(DustParams), _P, _I, C.c_float, _P, _P, _P, _P,
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_float)])
 _sig("tr_dust_equilibrium", _I, [_P, C.c_int64, _P, _P, _P, C.POINTER(DustParams), _P, _P, _P])
 _sig("tr_mlp_n_params", _I, [])
 _sig("tr_mlp_create", _I, [_P, _P, _P, C.POINTER(_P)])
@@ -186,6 +189,25 @@ def build_tree(ctx: Context, nb, max_level, blocks, x0, box_len, rho, kappa, t_d
     return Tree(ctx, h)
 
 
+def dust_fixed_point(ctx: Context, nb, max_level, blocks, x0, box_len, rho, t_gas, stars, sigma, c,
+                     tp: TraceParams, dp: DustParams, t_dust, J, F, u_rad, max_iter=20, tol=1e-4, mlp=None):
+    """tr_dust_fixed_point: t_dust (device float32) is the start and receives the result.
+    Returns (sweeps, last largest relative change)."""
+    blocks = np.ascontiguousarray(blocks, np.int32)
+    g = Grid(int(nb), int(max_level), int(blocks.shape[0]), _ptr(blocks),
+             (C.c_double * 3)(*[float(v) for v in x0]), float(box_len))
+    st = np.ascontiguousarray(np.asarray(stars, np.float64).reshape(-1, 4))
+    u = Units(float(sigma), float(c))
+    it = C.c_int32(0)
+    ch = C.c_float(0.0)
+    ctx.check(_lib.tr_dust_fixed_point(ctx.h, C.byref(g), _ptr(rho), _ptr(t_gas),
+                                       _ptr(st) if st.shape[0] else None, int(st.shape[0]), C.byref(u),
+                                       C.byref(tp), C.byref(dp), None if mlp is None else mlp.h,
+                                       int(max_iter), float(tol), _ptr(t_dust), _ptr(J), _ptr(F), _ptr(u_rad),
+                                       C.byref(it), C.byref(ch)))
+    return int(it.value), float(ch.value)
+
+
 def tree_export(ctx: Context, tree: Tree):
     n = tree.n_node
     out = dict(geo=np.zeros((n, 4), np.int32), meta=np.zeros(n, np.uint32),
@@ -197,11 +219,13 @@ def tree_export(ctx: Context, tree: Tree):
 
 
 def trace_params(n_side, theta=None, cube_m=0, merge=True, j_bg=0.0, bins_per_pass=0, chunk=0,
-                 waves_per_block=0, kernel=0) -> TraceParams:
-    """kernel: 0 automatic, 1 one wave per target, 2 one block per target."""
+                 waves_per_block=0, kernel=0, orientation=0, orient_seed=0) -> TraceParams:
+    """kernel: 0 automatic, 1 one wave per target, 2 one block per target.
+    orientation: 0..47 signed axis permutation of the ray set, -1 drawn per target."""
     th = (0, 0) if theta is None else theta
     return TraceParams(int(n_side), int(th[0]), int(th[1]), int(cube_m), int(bool(merge)),
-                       float(j_bg), int(bins_per_pass), int(chunk), int(waves_per_block), int(kernel))
+                       float(j_bg), int(bins_per_pass), int(chunk), int(waves_per_block), int(kernel),
+                       int(orientation), int(orient_seed))
 
 
 def trace_rays(ctx: Context, tree: Tree, p: TraceParams, J, F, u_rad=None):

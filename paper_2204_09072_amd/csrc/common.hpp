@@ -29,7 +29,8 @@ struct tr_ctx {
     hipStream_t stream = nullptr;
     int n_cu = 0;
     std::string err;
-    // device scratch: [0] work counter(s), [16] error word
+    // device scratch: [0..7] work counters, [16] trace error word, [17] tree error word,
+    // [24] largest relative change of a fixed-point sweep
     int *d_ctl = nullptr;
     std::map<std::pair<int, int>, RayTable> tables;
     // pinned host word for reading back the error flag

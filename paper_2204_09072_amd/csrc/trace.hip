@@ -73,6 +73,8 @@ struct TraceArgs {
     int kstack;     // ranges per wave stack
     int fcap;       // cooperative kernel: frontier capacity (child ranges per depth)
     int tab_slot;   // batched launches: which LDS table set the instance uses
+    int orient;     // ray-set orientation 0..47, -1 = drawn per target
+    uint32_t orient_seed;
     int per_block;  // waves per block
     int lds_wave;   // bytes of LDS per wave
     int lds_table;  // bytes of the shared tables (0: read the tables from global memory)
@@ -182,6 +184,52 @@ __device__ __forceinline__ bool one_face(int dx, int dy, int dz, int h) {
     return az - h2 > max(ax, ay);
 }
 
+// Orientation of the ray set (Sec. 7.6 names different HEALPix orientations as the remedy
+// for ray artefacts): one of the 48 signed permutations of the axes, which map the lattice
+// onto itself.  Index o: axis permutation o / 8 in the order 012 021 102 120 201 210, sign
+// flip of axis a for bit a of o % 8; a node offset d enters the angular kernel as
+// (s0 d[p0], s1 d[p1], s2 d[p2]).  A per-target draw takes the SplitMix64 generator
+// (Steele, Lea and Flood 2014) of seed * 2^32 + cell, modulo 48.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int target_orient(int orient, uint32_t seed, int cell) {
+    return orient >= 0 ? orient : (int)(splitmix64(((uint64_t)seed << 32) | (uint32_t)cell) % 48u);
+}
+
+__device__ __forceinline__ void orient_axes(int o, int &p0, int &p1, int &p2) {
+    const int q = o >> 3;
+    p0 = q >> 1;
+    p1 = (0x102021 >> (4 * q)) & 3; // 1 2 0 2 0 1
+    p2 = 3 - p0 - p1;
+}
+
+__device__ __forceinline__ void orient_offset(int o, int &x, int &y, int &z) {
+    if (o == 0) return;
+    int p0, p1, p2;
+    orient_axes(o, p0, p1, p2);
+    auto pick = [&](int k) { return k == 0 ? x : (k == 1 ? y : z); };
+    const int a = pick(p0), b = pick(p1), c = pick(p2);
+    x = (o & 1) ? -a : a;
+    y = (o & 2) ? -b : b;
+    z = (o & 4) ? -c : c;
+}
+
+// a vector from the ray set's frame back to the grid's axes: out[p_a] = s_a f[a]
+__device__ __forceinline__ void orient_back(int o, float &fx, float &fy, float &fz) {
+    if (o == 0) return;
+    int p0, p1, p2;
+    orient_axes(o, p0, p1, p2);
+    const float f0 = (o & 1) ? -fx : fx, f1 = (o & 2) ? -fy : fy, f2 = (o & 4) ? -fz : fz;
+    fx = p0 == 0 ? f0 : (p1 == 0 ? f1 : f2);
+    fy = p0 == 1 ? f0 : (p1 == 1 ? f1 : f2);
+    fz = p0 == 2 ? f0 : (p1 == 2 ? f1 : f2);
+}
+
 // Queue record of an accepted node: pk = content segment (i - a + 1, 0 = none) | first
 // merge flag << 6 | end of merge flags << 12 (both relative to the pass) | leaf << 18 |
 // depth << 19.
@@ -197,8 +245,9 @@ __device__ __forceinline__ bool one_face(int dx, int dy, int dz, int h) {
 // each (passes of up to 31 segments); otherwise both in flg (thick bits from bit 16).
 template <bool LDS_TABLE, bool ONE_FACE, bool SPLIT = false>
 __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *qnode, const uint32_t *qpk,
-                                          int pass_a, int4 c256, const uint8_t *tab8, const uint8_t *sqt,
-                                          float *bins, uint32_t *flg, float4 *thick, uint32_t *flgt = nullptr) {
+                                          int pass_a, int4 c256, int orient, const uint8_t *tab8,
+                                          const uint8_t *sqt, float *bins, uint32_t *flg, float4 *thick,
+                                          uint32_t *flgt = nullptr) {
     uint32_t starts = 0;
     int pix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     float Lt = 0, At = 0, LVk = 0, Ak = 0, Vk = 0, beta = 0;
@@ -226,7 +275,7 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             Lt = qv.x; LVk = qv.y; At = qv.z; Ak = qv.w;
             Vk = __int_as_float(p.w);
         }
-        const int dx = p.x - c256.x, dy = p.y - c256.y, dz = p.z - c256.z;
+        int dx = p.x - c256.x, dy = p.y - c256.y, dz = p.z - c256.z;
         if (seg >= 0) {
             // radial kernel beta = R_i^2 / r^2
             const int i = seg + pass_a;
@@ -234,6 +283,7 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             const float R2 = (float)(TR_FX * i * i);
             beta = (R2 * R2) * rcp(fx * fx + fy * fy + fz * fz);
         }
+        orient_offset(orient, dx, dy, dz); // the angular kernel works in the ray set's frame
         const int h = (TR_FX / 4) * s;
         auto lookup = [&](int cell) { return LDS_TABLE ? (int)tab8[cell] : (int)A.table[cell]; };
         bool single = false;
@@ -377,6 +427,7 @@ __device__ __forceinline__ void integrate_segment(const float *s, int i, float o
 struct Target {
     int tid, tx, ty, tz;
     int4 c256;
+    int orient;
 };
 struct PassGeo {
     int a, b, lo_cut, hi_cut, a4, b4;
@@ -479,7 +530,9 @@ __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const T
                     pk = (content ? (uint32_t)(i - G.a + 1) : 0u) | ((uint32_t)k0 << 6) |
                          ((uint32_t)k1 << 12) | ((leaf ? 1u : 0u) << 18) |
                          ((uint32_t)depth << 19);
-                    face1 = one_face(dx, dy, dz, (TR_FX / 4) * s);
+                    int ox = dx, oy = dy, oz = dz;
+                    orient_offset(T.orient, ox, oy, oz);
+                    face1 = one_face(ox, oy, oz, (TR_FX / 4) * s);
                 }
             }
         }
@@ -500,6 +553,7 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
     const int4 tr = A.nodes[tid];
     const int tx = tr.x & 0xffff, ty = tr.y & 0xffff, tz = tr.z;
     const int4 c256 = make_int4(tx * TR_FX, ty * TR_FX, tz * TR_FX, 0);
+    const int orient = target_orient(A.orient, A.orient_seed, A.leaf_cell[tid]);
     RayState<NSLOT> R;
 #pragma unroll
     for (int k = 0; k < NSLOT; ++k) {
@@ -629,7 +683,9 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                                     pk = (content ? (uint32_t)(i - P.a + 1) : 0u) | ((uint32_t)k0 << 6) |
                                          ((uint32_t)k1 << 12) | ((leaf ? 1u : 0u) << 18) |
                                          ((uint32_t)depth << 19);
-                                    face1 = one_face(dx, dy, dz, (TR_FX / 4) * s);
+                                    int ox = dx, oy = dy, oz = dz;
+                                    orient_offset(orient, ox, oy, oz);
+                                    face1 = one_face(ox, oy, oz, (TR_FX / 4) * s);
                                 }
                             }
                         }
@@ -664,14 +720,14 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
             if (qf >= 64 || (sp == 0 && qf > 0)) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = lane < nq ? qf - nq + lane : -1;
-                map_queue<LDS_TABLE, true>(A, e, qnode, qpk, P.a, c256, tab8, sqt, bins, flg, thick);
+                map_queue<LDS_TABLE, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flg, thick);
                 qf -= nq;
                 wave_sync();
             }
             if (qs >= 64 || (sp == 0 && qs > 0)) {
                 const int nq = qs >= 64 ? 64 : qs;
                 const int e = lane < nq ? kQueue - qs + lane : -1;
-                map_queue<LDS_TABLE, false>(A, e, qnode, qpk, P.a, c256, tab8, sqt, bins, flg, thick);
+                map_queue<LDS_TABLE, false>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flg, thick);
                 qs -= nq;
                 wave_sync();
             }
@@ -774,6 +830,7 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
             const float e = (float)(A.root_edge >> ((tr.x >> 16) & 15));
             Jv += -expm1f(-0.5f * A.cell_tau[cell]) * src / (4.0f * kPiF * (e * e));
         }
+        orient_back(orient, fx, fy, fz); // the flux back to the grid's axes
         A.J[cell] = Jv;
         A.F[cell] = fx;
         A.F[A.n_cells + cell] = fy;
@@ -865,7 +922,8 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
     const int4 tr = A.nodes[tid];
     const int tx = tr.x & 0xffff, ty = tr.y & 0xffff, tz = tr.z;
     const int4 c256 = make_int4(tx * TR_FX, ty * TR_FX, tz * TR_FX, 0);
-    const Target T{tid, tx, ty, tz, c256};
+    const int orient = target_orient(A.orient, A.orient_seed, A.leaf_cell[tid]);
+    const Target T{tid, tx, ty, tz, c256, orient};
     // ray state of this thread's ray (threads 0 .. npix-1)
     const int h = threadIdx.x;
     const bool ray = h < A.npix;
@@ -938,14 +996,14 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
                         wave_sync();
                         if (qf >= 64) {
                             const int e = qf - 64 + lane;
-                            map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, tab8, sqt, bins, flgm, thick,
+                            map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flgm, thick,
                                                         flgt);
                             qf -= 64;
                             wave_sync();
                         }
                         if (qs >= 64) {
                             const int e = kQueue - qs + lane;
-                            map_queue<true, false, true>(A, e, qnode, qpk, P.a, c256, tab8, sqt, bins, flgm, thick,
+                            map_queue<true, false, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flgm, thick,
                                                          flgt);
                             qs -= 64;
                             wave_sync();
@@ -962,14 +1020,14 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
             if (qf > 0) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = lane < nq ? qf - nq + lane : -1;
-                map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, tab8, sqt, bins, flgm, thick, flgt);
+                map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flgm, thick, flgt);
                 qf -= nq;
                 wave_sync();
             }
             if (qs > 0) {
                 const int nq = qs >= 64 ? 64 : qs;
                 const int e = lane < nq ? kQueue - qs + lane : -1;
-                map_queue<true, false, true>(A, e, qnode, qpk, P.a, c256, tab8, sqt, bins, flgm, thick, flgt);
+                map_queue<true, false, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flgm, thick, flgt);
                 qs -= nq;
                 wave_sync();
             }
@@ -1051,6 +1109,7 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
             const float e = (float)(A.root_edge >> ((tr.x >> 16) & 15));
             Jv += -expm1f(-0.5f * A.cell_tau[cell]) * src / (4.0f * kPiF * (e * e));
         }
+        orient_back(orient, fx, fy, fz); // the flux back to the grid's axes
         A.J[cell] = Jv;
         A.F[cell] = fx;
         A.F[A.n_cells + cell] = fy;
@@ -1251,6 +1310,10 @@ int setup_instance(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, floa
     A.c_light = (float)t->c_light;
     A.kstack = stack_size(t->D);
     A.tab_slot = 0;
+    if (p->orientation < -1 || p->orientation > 47)
+        return tr_fail(ctx, TR_EINVAL, "orientation must be -1 (per target) or 0..47");
+    A.orient = p->orientation;
+    A.orient_seed = p->orient_seed;
     return TR_OK;
 }
 

@@ -1,0 +1,71 @@
+"""Steps around the hot path, on the GPU through the C ABI against the FP64 oracle:
+the self-consistent dust temperature (repeated build -> trace -> equilibrium)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+from test_gpu_parity import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_09072_amd as T
+    return T
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def test_dust_fixed_point_parity(lib, ctx):
+    """Three sweeps on a 32^3 collapsing core.  Per sweep the trace carries J to 1e-4 and
+    T_dust follows J^(1/4..1/6) while the next emission follows T^6, so the error grows
+    about linearly with the sweeps: bars 3e-4 on T_dust and 1e-3 on J after three."""
+    import torch
+    from paper_2204_09072_amd.run import params_of, upload
+    w = W.c3_core128(n=32, n_side=2)
+    dev = upload(w)
+    n = w.n_cells
+    td = dev["t_dust"].clone()
+    J = torch.empty(n, device="cuda")
+    F = torch.empty((3, n), device="cuda")
+    U = torch.empty(n, device="cuda")
+    say("fixed point 32^3, 3 sweeps")
+    sweeps, change = lib.dust_fixed_point(ctx, w.nb, w.max_level, w.blocks, w.x0, w.box_len, dev["rho"],
+                                          dev["t_gas"], w.stars, w.units[0], w.units[1], params_of(w),
+                                          lib.dust_params(w.units[0], w.units[1]), td, J, F, U,
+                                          max_iter=3, tol=0.0)
+    ctx.sync()
+    assert sweeps == 3
+    To, Jo, Fo, ch = oracle.dust_fixed_point(w, 3)
+    T = td.cpu().numpy()
+    rt = np.abs(T - To) / To
+    rj = np.abs(J.cpu().numpy() - Jo) / Jo
+    say("  T_dust max rel %.2e, J max rel %.2e, change %.4f vs %.4f" % (rt.max(), rj.max(), change, ch[-1]))
+    assert rt.max() < 3e-4
+    assert rj.max() < 1e-3
+    assert change == pytest.approx(ch[-1], rel=1e-2)
+
+
+@pytest.mark.parametrize("orient,seed,kernel", [(13, 0, 1), (42, 0, 2), (-1, 5, 1), (-1, 9, 2)])
+def test_trace_orientation_parity(lib, ctx, orient, seed, kernel):
+    """Re-oriented ray sets (Sec. 7.6), fixed or drawn per target, on a grid with stars
+    and no symmetry, both trace kernels, every target against the oracle."""
+    from paper_2204_09072_amd.run import trace
+    from test_gpu_parity import TREE_CASES, _check_trace
+    w = TREE_CASES["padded40"]()
+    say("orientation", orient, "seed", seed, "kernel", kernel)
+    tree, J, F, U = trace(ctx, w, orientation=orient, orient_seed=seed, kernel=kernel)
+    ctx.sync()
+    Jo, Fo = oracle.Tree(w).trace(oracle.params(w.n_side, theta=w.theta, orient=orient, orient_seed=seed))
+    _check_trace(J.cpu().numpy(), F.cpu().numpy().T, Jo, Fo)

@@ -475,3 +475,78 @@ def test_mlp_gradient_finite_differences():
         pm = prm.copy(); pm[idx] -= eps
         fd = (oracle.mlp(H, pp, x, y, grad=False)[0] - oracle.mlp(H, pm, x, y, grad=False)[0]) / (2 * eps)
         assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-9)
+
+
+# ----------------------------------------------------------------------------------
+# self-consistent dust temperature (Sec. 2, 4.1, 4.6)
+# ----------------------------------------------------------------------------------
+def test_fixed_point_strong_coupling_is_gas_temperature():
+    """With a gas-dust coupling far above the radiative rates the dust takes the gas
+    temperature after one sweep, and a further sweep leaves it there."""
+    w = W.c3_core128(n=16, n_side=1)
+    T, J, F, ch = oracle.dust_fixed_point(w, 2, c_gd=1e-10)
+    assert np.allclose(T, w.t_gas.astype(np.float64), rtol=1e-6)
+    assert ch[1] < 1e-6
+
+
+def test_fixed_point_thick_isothermal_box_stays_at_gas_temperature():
+    """An optically thick box (cells of optical depth ~5) of gas and dust at one temperature
+    is a fixed point in its interior: there J = B(T_dust) (Kirchhoff limit, App. B), the
+    radiative terms cancel and the gas coupling holds T_dust = T_gas."""
+    n, T0 = 16, 20.0
+    box = 0.01 * W.PC
+    rho = 1e-14                                   # kappa_P(20 K) rho dx = 0.4 * 1e-14 * 1.9e15 ~ 7.7
+    shape = (n, n, n)
+    w = W.synth._uniform_workload("thickbox", np.full(shape, rho), np.full(shape, T0), None, n // 8, box,
+                                  W.CGS_UNITS, 1, np.zeros((0, 4)), t_gas3=np.full(shape, T0), cgs=True)
+    T, J, F, ch = oracle.dust_fixed_point(w, 2)
+    x = cell_centres(w) / box
+    inner = np.all(np.abs(x - 0.5) < 0.2, axis=1)
+    assert np.abs(T[inner] / T0 - 1).max() < 1e-3
+    assert T[~inner].min() < T0            # the surface cools into the empty surroundings
+
+
+# ----------------------------------------------------------------------------------
+# orientations of the ray set (Sec. 7.6)
+# ----------------------------------------------------------------------------------
+_PERMS = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+
+
+def _apply(o, v):
+    """Signed axis permutation o applied to vectors v [..., 3]: w_a = s_a v[p_a]."""
+    p = _PERMS[o >> 3]
+    s = np.array([-1.0 if (o >> a) & 1 else 1.0 for a in range(3)])
+    return np.stack([s[a] * v[..., p[a]] for a in range(3)], axis=-1)
+
+
+@pytest.mark.parametrize("o", [5, 13, 42])
+def test_orientation_is_covariant_on_a_symmetric_grid(o):
+    """The 16^3 sphere is invariant under every signed axis permutation P about the box
+    centre, so tracing cell c with the ray set oriented by P must see what the identity
+    ray set sees from cell P c: J_o(c) = J(P c) and F_o(c) = P^-1 F(P c)."""
+    w = W.c1_sphere16()
+    t = oracle.Tree(w)
+    J0, F0 = t.trace(oracle.params(1))
+    x = cell_centres(w) - 0.5
+    cells = np.arange(0, w.n_cells, 37)
+    Jo, Fo = t.trace(oracle.params(1, orient=o), cells=cells)
+    # the cell at P (x_c - centre)
+    y = _apply(o, x[cells])
+    lut = {tuple(np.round(v * 32).astype(int)): k for k, v in enumerate(x)}
+    img = np.array([lut[tuple(np.round(v * 32).astype(int))] for v in y])
+    assert np.allclose(Jo, J0[img], rtol=1e-9, atol=0)
+    # F(P c) = P F_o(c)
+    assert np.allclose(_apply(o, Fo), F0[img], rtol=1e-7, atol=1e-9 * np.abs(J0).max())
+
+
+def test_orientation_keeps_the_inverse_square_law():
+    """Any orientation, fixed or drawn per target, maps a lone star's light whole
+    (sum of alpha = 1): J r^2 = L / (16 pi^2) to rounding at every non-host cell."""
+    n = 16
+    w = W.point_source_box(n, 0.0, n_side=2)
+    t = oracle.Tree(w)
+    r = np.linalg.norm(cell_centres(w) - (0.5 + 0.5 / n), axis=1)   # the host cell's centre
+    m = r > 1e-12
+    for prm in (oracle.params(2, orient=29), oracle.params(2, orient=-1, orient_seed=7)):
+        J, F = t.trace(prm)
+        assert np.allclose(J[m] * r[m] ** 2 * 16 * np.pi ** 2, 1.0, rtol=1e-9)
