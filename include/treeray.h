@@ -233,6 +233,33 @@ int tr_mlp_grad(tr_ctx *ctx, const tr_mlp *mlp, int64_t n, const float *x, const
 int tr_mlp_train_step(tr_ctx *ctx, tr_mlp *mlp, int64_t n, const float *x, const float *y,
                       float lr, float *loss);
 
+/* Ionising side of the stellar sources (Sec. 7.2).  Per star: T_int = (L_int / (4 pi
+ * sigma r^2))^(1/4), T_acc = (L_acc / (f_fill 4 pi sigma r^2))^(1/4), gamma(T) = fraction of a
+ * black body's power above the Lyman limit (t_lyc = h nu_LyC / k, 157 821 K for 13.6 eV),
+ * L_uv = gamma(T_int) L_int + gamma(T_acc) L_acc, L_ir = L_int + L_acc - L_uv (the L_IR
+ * that tr_build_tree takes).  All arrays device double[n]; FP64. */
+int tr_star_luminosity_split(tr_ctx *ctx, int n, const double *L_int, const double *L_acc,
+                             const double *r_star, double f_fill, double sigma, double t_lyc,
+                             double *L_uv, double *L_ir);
+
+/* UV radiation pressure (App. C) for an ionising photon number flux n_ph (photons per unit
+ * area and time, from the ionising-radiation solver) of mean energy e_ph along the unit
+ * vector u_ph: momentum rates per volume on dust sigma_d n (e_ph/c) n_ph, on neutral
+ * hydrogen sigma_h (1 - x) n (e_ph/c) n_ph and on ionised hydrogen alpha_b (x n)^2 (e_ph/c)
+ * (recombinations balanced by absorptions), n = rho / mu_mh, x = ionised fraction.
+ * a_uv = (their sum) u_ph / rho.  rho, x_ion, n_ph: device float[n]; u_ph, a_uv: device
+ * float[3][n]; parts: device float[3][n] (dust, H, H+) or NULL. */
+typedef struct tr_uv_params {
+    double e_ph;    /* mean ionising photon energy */
+    double sigma_d; /* dust cross section per hydrogen nucleus (1.5e-21 cm^2 in the paper) */
+    double sigma_h; /* hydrogen photoionisation cross section */
+    double alpha_b; /* case-B recombination coefficient */
+    double mu_mh;   /* mass per hydrogen nucleus (1.4 m_H) */
+    double c;
+} tr_uv_params;
+int tr_uv_rad_pressure(tr_ctx *ctx, int64_t n, const float *rho, const float *x_ion, const float *n_ph,
+                       const float *u_ph, const tr_uv_params *p, float *a_uv, float *parts);
+
 /* Context: one HIP device and stream (hipStream_t passed as void*, NULL = null stream). */
 int tr_ctx_create(tr_ctx **out, int device, void *stream);
 void tr_ctx_destroy(tr_ctx *ctx);

@@ -63,6 +63,10 @@ def lib():
                                  C.c_double, P, P]
         L.or_dust_residual.restype = C.c_double
         L.or_dust_residual.argtypes = [C.c_double] * 8
+        L.or_lyman_fraction.restype = C.c_double
+        L.or_lyman_fraction.argtypes = [C.c_double, C.c_double]
+        L.or_luminosity_split.argtypes = [C.c_int, P, P, P, C.c_double, C.c_double, C.c_double, P, P]
+        L.or_uv_rad_pressure.argtypes = [C.c_int64, P, P, P, P] + [C.c_double] * 6 + [P, P]
         L.or_mlp.restype = C.c_double
         L.or_mlp.argtypes = [C.c_int, P, C.c_int64, P, P, C.c_int, P, P]
         _lib = L
@@ -259,3 +263,34 @@ def dust_fixed_point(w, n_iter, c_gd=3.8e-33, xi=1.0, tol=0.0, prm=None):
         if ch <= tol:
             break
     return T, J, F, changes
+
+
+T_LYC = 13.6 * 1.602176634e-12 / 1.380649e-16   # h nu_LyC / k_B in K (13.6 eV)
+
+
+def lyman_fraction(T, t_lyc=T_LYC):
+    """Fraction of a black body's power above the Lyman limit (Sec. 7.2)."""
+    return lib().or_lyman_fraction(float(T), float(t_lyc))
+
+
+def luminosity_split(L_int, L_acc, r_star, sigma, f_fill=0.1, t_lyc=T_LYC):
+    """(L_uv, L_ir) of stars with internal and accretion luminosities (Sec. 7.2)."""
+    a = [np.ascontiguousarray(v, np.float64) for v in (L_int, L_acc, r_star)]
+    n = a[0].shape[0]
+    uv, ir = np.zeros(n), np.zeros(n)
+    lib().or_luminosity_split(n, _p(a[0]), _p(a[1]), _p(a[2]), float(f_fill), float(sigma), float(t_lyc),
+                              _p(uv), _p(ir))
+    return uv, ir
+
+
+def uv_rad_pressure(rho, x_ion, nph, uph, e_ph, sigma_d=1.5e-21, sigma_h=6.3e-18, alpha_b=2.6e-13,
+                    mu_mh=1.4 * 1.6735575e-24, c=2.99792458e10):
+    """App. C: acceleration [n, 3] and momentum rates per volume on dust, H, H+ [n, 3]."""
+    rho, x, N = (np.ascontiguousarray(v, np.float64) for v in (rho, x_ion, nph))
+    u = np.ascontiguousarray(uph, np.float64).reshape(-1, 3)
+    n = rho.shape[0]
+    a = np.zeros((n, 3))
+    parts = np.zeros((n, 3))
+    lib().or_uv_rad_pressure(n, _p(rho), _p(x), _p(N), _p(u), float(e_ph), float(sigma_d), float(sigma_h),
+                             float(alpha_b), float(mu_mh), float(c), _p(a), _p(parts))
+    return a, parts

@@ -86,6 +86,18 @@ void or_dust_eq(int64_t n, const double *rho, const double *u_rad, const double 
 double or_dust_residual(double T, double rho, double u_rad, double t_gas, double sigma,
                         double c, double c_gd, double xi);
 
+/* Lyman-continuum fraction of a black body (Sec. 7.2), t_lyc = h nu_LyC / k. */
+double or_lyman_fraction(double T, double t_lyc);
+/* Split of internal and accretion luminosities into ionising L_uv and non-ionising L_ir
+ * (Sec. 7.2; hot-spot filling factor f_fill). */
+void or_luminosity_split(int n, const double *L_int, const double *L_acc, const double *r_star,
+                         double f_fill, double sigma, double t_lyc, double *L_uv, double *L_ir);
+/* UV radiation pressure (App. C): acceleration a[n][3] and, if parts != NULL, the momentum
+ * rates per volume on dust, H and H+ [n][3]. */
+void or_uv_rad_pressure(int64_t n, const double *rho, const double *x_ion, const double *nph,
+                        const double *uph, double e_ph, double sigma_d, double sigma_h, double alpha_b,
+                        double mu_mh, double c, double *a, double *parts);
+
 /* MLP 3 -> H -> H -> 1 (tanh), FP64 forward and backward for a batch; parameter
  * layout W1[H][3] b1[H] W2[H][H] b2[H] W3[H] b3.  round_bf16 != 0 rounds each layer's
  * input activations to bfloat16 (as the GPU's MFMA operands).  Returns the mean

@@ -18,7 +18,8 @@
  *
  * Parity unpinned: the host-cell source terms J_src (Sec. 4.4) and P_src (Sec. 4.5) follow
  * a reading of definitions the paper leaves open (the source volume and area); nothing
- * outside this code fixes their values, so only their limits are tested.  Only the tests, the smoke check and the benchmark's CPU-baseline
+ * outside this code fixes their values, so only their limits are tested.  Likewise the UV
+ * radiation-pressure rates of App. C, which are the paper's expressions restated.  Only the tests, the smoke check and the benchmark's CPU-baseline
  * leg load this code; it shares nothing with the library under paper_2204_09072_amd/.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared  (no fast-math: the fixed
@@ -936,4 +937,74 @@ double or_mlp(int H, const double *prm, int64_t n, const double *x, const double
     }
     free(h1); free(h2); free(d2); free(d1);
     return n > 0 ? loss / (double)n : 0.0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Stellar luminosity split (Sec. 7.2) and UV radiation pressure (App. C)
+ * ---------------------------------------------------------------------------------- */
+/* Lyman-continuum fraction of a black body at temperature T (eq. for gamma(T_X) in
+ * Sec. 7.2): with x0 = h nu_LyC / (k T) = t_lyc / T and the Planck integral
+ * I(x0) = int_x0^inf x^3 / (e^x - 1) dx, gamma = I(x0) / I(0), I(0) = pi^4 / 15.
+ * x0 >= 2: I = sum_k e^{-k x0} (x0^3/k + 3 x0^2/k^2 + 6 x0/k^3 + 6/k^4) (term-wise
+ * integration of the geometric series of 1/(e^x - 1)); x0 < 2: I = pi^4/15 - int_0^x0,
+ * with x/(e^x - 1) = sum_n B_n x^n / n! (Bernoulli numbers, |x| < 2 pi) integrated
+ * term by term: int_0^x0 = sum_n B_n x0^(n+3) / (n! (n+3)). */
+double or_lyman_fraction(double T, double t_lyc) {
+    if (!(T > 0.0)) return 0.0;
+    const double x0 = t_lyc / T;
+    const double I0 = pow(M_PI, 4) / 15.0;
+    if (x0 >= 2.0) {
+        double s = 0.0;
+        for (int k = 1; k <= 200; ++k) {
+            double e = exp(-k * x0);
+            double term = e * (x0 * x0 * x0 / k + 3.0 * x0 * x0 / ((double)k * k) +
+                               6.0 * x0 / ((double)k * k * k) + 6.0 / ((double)k * k * k * k));
+            s += term;
+            if (term < 1e-18 * s) break;
+        }
+        return s / I0;
+    }
+    /* Bernoulli numbers B_0 .. B_30 (B_1 = -1/2, odd ones beyond vanish) */
+    static const double B[31] = {1.0, -0.5, 1.0 / 6, 0, -1.0 / 30, 0, 1.0 / 42, 0, -1.0 / 30, 0, 5.0 / 66, 0,
+                                 -691.0 / 2730, 0, 7.0 / 6, 0, -3617.0 / 510, 0, 43867.0 / 798, 0,
+                                 -174611.0 / 330, 0, 854513.0 / 138, 0, -236364091.0 / 2730, 0,
+                                 8553103.0 / 6, 0, -23749461029.0 / 870, 0, 8615841276005.0 / 14322};
+    double low = 0.0, fact = 1.0, pw = x0 * x0 * x0;
+    for (int n = 0; n <= 30; ++n) {
+        if (n > 0) fact *= n;
+        low += B[n] * pw / (fact * (n + 3));
+        pw *= x0;
+    }
+    return (I0 - low) / I0;
+}
+
+void or_luminosity_split(int n, const double *L_int, const double *L_acc, const double *r_star,
+                         double f_fill, double sigma, double t_lyc, double *L_uv, double *L_ir) {
+    for (int s = 0; s < n; ++s) {
+        /* effective temperatures of the photosphere and of the accretion hot spots */
+        double area = 4.0 * M_PI * r_star[s] * r_star[s];
+        double T_int = pow(L_int[s] / (sigma * area), 0.25);
+        double T_acc = pow(L_acc[s] / (f_fill * sigma * area), 0.25);
+        double uv = or_lyman_fraction(T_int, t_lyc) * L_int[s] + or_lyman_fraction(T_acc, t_lyc) * L_acc[s];
+        L_uv[s] = uv;
+        L_ir[s] = L_int[s] + L_acc[s] - uv;
+    }
+}
+
+/* App. C: momentum deposited per unit time and volume on dust (sigma_d n), neutral
+ * hydrogen (sigma_H n_H0) and, through recombinations balanced by absorptions, ionised
+ * hydrogen (alpha_B n_H+^2), for a photon number flux N of mean energy E along u; n =
+ * rho / (mu m_H) hydrogen nuclei, n_H0 = (1 - x) n, n_H+ = x n.  a = total / rho. */
+void or_uv_rad_pressure(int64_t n, const double *rho, const double *x_ion, const double *nph,
+                        const double *uph, double e_ph, double sigma_d, double sigma_h, double alpha_b,
+                        double mu_mh, double c, double *a, double *parts) {
+    for (int64_t i = 0; i < n; ++i) {
+        double nh = rho[i] / mu_mh, x = x_ion[i];
+        double p = e_ph / c;
+        double pd = sigma_d * nh * p * nph[i];
+        double ph = sigma_h * (1.0 - x) * nh * p * nph[i];
+        double pi = (x * nh) * (x * nh) * alpha_b * p;
+        for (int k = 0; k < 3; ++k) a[3 * i + k] = (pd + ph + pi) * uph[3 * i + k] / rho[i];
+        if (parts) { parts[3 * i] = pd; parts[3 * i + 1] = ph; parts[3 * i + 2] = pi; }
+    }
 }

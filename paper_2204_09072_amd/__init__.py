@@ -58,6 +58,11 @@ class BatchTuning(C.Structure):
                 ("sample_ms", C.c_float)]
 
 
+class UvParams(C.Structure):
+    _fields_ = [("e_ph", C.c_double), ("sigma_d", C.c_double), ("sigma_h", C.c_double),
+                ("alpha_b", C.c_double), ("mu_mh", C.c_double), ("c", C.c_double)]
+
+
 class DustParams(C.Structure):
     _fields_ = [("sigma", C.c_double), ("c", C.c_double), ("c_gd", C.c_double), ("xi", C.c_double),
                 ("rel_tol", C.c_float), ("max_iter", C.c_int32), ("start", C.c_int32), ("linear", C.c_int32)]
@@ -93,6 +98,8 @@ _sig("tr_rad_force", _I, [_P, _P, _P, _P, _P])
 _sig("tr_dust_fixed_point", _I, [_P, C.POINTER(Grid), _P, _P, _P, _I, C.POINTER(Units), C.POINTER(TraceParams),
                                   C.POINTER(DustParams), _P, _I, C.c_float, _P, _P, _P, _P,
                                   C.POINTER(C.c_int32), C.POINTER(C.c_float)])
+_sig("tr_star_luminosity_split", _I, [_P, _I, _P, _P, _P, C.c_double, C.c_double, C.c_double, _P, _P])
+_sig("tr_uv_rad_pressure", _I, [_P, C.c_int64, _P, _P, _P, _P, C.POINTER(UvParams), _P, _P])
 _sig("tr_dust_equilibrium", _I, [_P, C.c_int64, _P, _P, _P, C.POINTER(DustParams), _P, _P, _P])
 _sig("tr_mlp_n_params", _I, [])
 _sig("tr_mlp_create", _I, [_P, _P, _P, C.POINTER(_P)])
@@ -206,6 +213,26 @@ def dust_fixed_point(ctx: Context, nb, max_level, blocks, x0, box_len, rho, t_ga
                                        int(max_iter), float(tol), _ptr(t_dust), _ptr(J), _ptr(F), _ptr(u_rad),
                                        C.byref(it), C.byref(ch)))
     return int(it.value), float(ch.value)
+
+
+T_LYC = 13.6 * 1.602176634e-12 / 1.380649e-16   # h nu_LyC / k_B in K
+
+
+def star_luminosity_split(ctx: Context, L_int, L_acc, r_star, sigma, L_uv, L_ir, f_fill=0.1, t_lyc=T_LYC):
+    """tr_star_luminosity_split on device float64 arrays."""
+    ctx.check(_lib.tr_star_luminosity_split(ctx.h, int(L_int.numel()), _ptr(L_int), _ptr(L_acc), _ptr(r_star),
+                                            float(f_fill), float(sigma), float(t_lyc), _ptr(L_uv), _ptr(L_ir)))
+
+
+def uv_params(e_ph, sigma_d=1.5e-21, sigma_h=6.3e-18, alpha_b=2.6e-13, mu_mh=1.4 * 1.6735575e-24,
+              c=2.99792458e10) -> UvParams:
+    return UvParams(float(e_ph), float(sigma_d), float(sigma_h), float(alpha_b), float(mu_mh), float(c))
+
+
+def uv_rad_pressure(ctx: Context, rho, x_ion, n_ph, u_ph, p: UvParams, a_uv, parts=None):
+    """tr_uv_rad_pressure: rho, x_ion, n_ph [n]; u_ph, a_uv, parts [3, n] (device float32)."""
+    ctx.check(_lib.tr_uv_rad_pressure(ctx.h, int(rho.numel()), _ptr(rho), _ptr(x_ion), _ptr(n_ph), _ptr(u_ph),
+                                      C.byref(p), _ptr(a_uv), _ptr(parts)))
 
 
 def tree_export(ctx: Context, tree: Tree):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtreeray.so")
-SOURCES = ["runtime.hip", "tree.hip", "rays.hip", "trace.hip", "dust.hip", "mlp.hip", "fixed_point.hip"]
+SOURCES = ["runtime.hip", "tree.hip", "rays.hip", "trace.hip", "dust.hip", "mlp.hip", "fixed_point.hip", "uv.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off",                      # fixed FP64 operation order in the tree build

@@ -550,3 +550,58 @@ def test_orientation_keeps_the_inverse_square_law():
     for prm in (oracle.params(2, orient=29), oracle.params(2, orient=-1, orient_seed=7)):
         J, F = t.trace(prm)
         assert np.allclose(J[m] * r[m] ** 2 * 16 * np.pi ** 2, 1.0, rtol=1e-9)
+
+
+# ----------------------------------------------------------------------------------
+# stellar luminosity split (Sec. 7.2) and UV radiation pressure (App. C)
+# ----------------------------------------------------------------------------------
+def test_lyman_fraction_against_quadrature_and_limits():
+    """gamma(T) = int_{nu_LyC} B_nu / int_0 B_nu: numerical quadrature of the Planck
+    integral at several temperatures (both series branches of the oracle), the Wien tail
+    at low T and the limit 1 at high T."""
+    from scipy.integrate import quad
+    def f(x):
+        with np.errstate(over="ignore"):
+            return x ** 3 / np.expm1(x)
+    I0 = np.pi ** 4 / 15
+    for T in (5e3, 1e4, 3e4, 6e4, 7.9e4, 8.0e4, 2e5, 1e6, 1e7):
+        x0 = oracle.T_LYC / T
+        ref = quad(f, x0, np.inf, epsabs=0, epsrel=1e-13, limit=200)[0] / I0
+        assert oracle.lyman_fraction(T) == pytest.approx(ref, rel=1e-9, abs=1e-300), T
+    x0 = oracle.T_LYC / 3000.0
+    wien = 15 / np.pi ** 4 * np.exp(-x0) * (x0 ** 3 + 3 * x0 ** 2 + 6 * x0 + 6)
+    assert oracle.lyman_fraction(3000.0) == pytest.approx(wien, rel=1e-12)
+    assert oracle.lyman_fraction(1e12) == pytest.approx(1.0, abs=1e-6)
+    assert oracle.lyman_fraction(0.0) == 0.0
+
+
+def test_luminosity_split_conserves_and_orders():
+    """L_uv + L_ir = L_int + L_acc; hotter (smaller, or accreting on a small filling factor)
+    stars put a larger share into the Lyman continuum."""
+    rsun, lsun = 6.957e10, 3.828e33
+    L_int = np.array([1e3, 1e3, 1e4]) * lsun
+    L_acc = np.array([0.0, 1e3, 1e2]) * lsun
+    r = np.array([5.0, 5.0, 3.0]) * rsun
+    uv, ir = oracle.luminosity_split(L_int, L_acc, r, W.SIGMA_SB)
+    assert np.allclose(uv + ir, L_int + L_acc, rtol=1e-14)
+    assert np.all(uv >= 0) and np.all(ir > 0)
+    assert uv[1] > uv[0]                       # accretion hot spots add ionising power
+    T = (L_int / (W.SIGMA_SB * 4 * np.pi * r ** 2)) ** 0.25
+    assert uv[0] == pytest.approx(oracle.lyman_fraction(T[0]) * L_int[0], rel=1e-14)
+
+
+def test_uv_rad_pressure_limits():
+    """App. C limits: a neutral cell gets no recombination term, a fully ionised one no
+    neutral-hydrogen term; the dust and neutral terms scale with the photon flux and the
+    recombination term with the square of the ionised density (parity otherwise unpinned:
+    the three rates are the paper's expressions restated)."""
+    rho = np.array([1e-20, 1e-20, 1e-20, 2e-20])
+    x = np.array([0.0, 1.0, 0.5, 0.5])
+    N = np.array([1e10, 1e10, 1e10, 1e10])
+    u = np.tile([0.0, 0.6, 0.8], (4, 1))
+    a, p = oracle.uv_rad_pressure(rho, x, N, u, 20 * 1.602e-12)
+    assert p[0, 2] == 0.0 and p[1, 1] == 0.0
+    assert p[3, 2] == pytest.approx(4 * p[2, 2], rel=1e-14)
+    a2, p2 = oracle.uv_rad_pressure(rho, x, 2 * N, u, 20 * 1.602e-12)
+    assert np.allclose(p2[:, :2], 2 * p[:, :2], rtol=1e-14) and np.allclose(p2[:, 2], p[:, 2], rtol=1e-14)
+    assert np.allclose(np.linalg.norm(a, axis=1), p.sum(axis=1) / rho, rtol=1e-14)
