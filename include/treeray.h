@@ -115,6 +115,9 @@ typedef struct tr_trace_params {
                               passes of bins_per_pass radial points), 2 = one block of waves
                               per target (all segments in LDS, one walk; needs N_side <= 4 and
                               an opening angle >= 1/8) */
+    int32_t per_node_kernel; /* 0 = tabulated angular kernel (tr_alpha_table) for nodes at
+                              least 8 edges away and the per-node 8-point kernel for nearer
+                              ones; 1 = the per-node kernel for every node */
     int32_t orientation;   /* orientation of the ray set (Sec. 7.6): 0 = HEALPix axes, 1..47 =
                               a signed permutation of the axes applied to every target (axis
                               permutation o / 8 in the order 012 021 102 120 201 210, sign
@@ -168,6 +171,12 @@ int tr_walk_counts(tr_ctx *ctx, const tr_tree *tree, const tr_trace_params *p,
 /* Angular kernel table [6][M][M] (pixel id of each direction cell) and ray directions
  * [N_pix][3], built on the device and copied to HOST buffers; synchronous. */
 int tr_ray_tables(tr_ctx *ctx, int n_side, int cube_m, int32_t *table, float *dirs);
+
+/* Tabulated angular kernel (Sec. 4.2.1) that nodes at least 8 edges away use: HOST
+ * int32[6 M M][15][9], per direction cell and distance class c = floor(log2(r^2 / s^2)) =
+ * 6 .. 20, pixels 0..3 (ascending), their counts out of 64 sub-points, and a flag for keys
+ * whose sub-points reach more than 4 pixels (served by the per-node kernel); synchronous. */
+int tr_alpha_table(tr_ctx *ctx, int n_side, int cube_m, int32_t *out);
 
 /* Radiation pressure (Sec. 4.5): a_RP = kappa F / c (1 - e^-tau)/tau with the factor 1
  * below tau = 1e-4, tau = rho kappa dx of the cell; P_src = (1 - e^{-tau/2}) L / (c dV^(2/3))

@@ -52,6 +52,7 @@ def lib():
         L.or_vec2pix.restype = C.c_int
         L.or_vec2pix.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
         L.or_cube_table.argtypes = [C.c_int, C.c_int, P]
+        L.or_alpha_table.argtypes = [C.c_int, P, P]
         L.or_trace.restype = C.c_int
         L.or_trace.argtypes = [P, P, C.c_int64, P, P, P, P, C.c_int]
         L.or_trace_one.restype = C.c_int
@@ -80,15 +81,16 @@ def _p(a):
 class _Params(C.Structure):
     _fields_ = [("n_side", C.c_int), ("theta_num", C.c_int), ("theta_den", C.c_int),
                 ("cube_m", C.c_int), ("merge", C.c_int), ("j_bg", C.c_double),
-                ("orient", C.c_int), ("orient_seed", C.c_uint)]
+                ("orient", C.c_int), ("orient_seed", C.c_uint), ("alpha_table", C.c_int)]
 
 
-def params(n_side, theta=None, cube_m=None, merge=True, j_bg=0.0, orient=0, orient_seed=0):
-    """orient: 0..47 signed axis permutation of the ray set, -1 drawn per target cell."""
+def params(n_side, theta=None, cube_m=None, merge=True, j_bg=0.0, orient=0, orient_seed=0, alpha_table=True):
+    """orient: 0..47 signed axis permutation of the ray set, -1 drawn per target cell.
+    alpha_table: tabulated angular kernel for nodes at least 8 edges away."""
     theta = (1, 2 * n_side) if theta is None else theta
     cube_m = DEFAULT_CUBE_PER_NSIDE * n_side if cube_m is None else cube_m
     return _Params(int(n_side), int(theta[0]), int(theta[1]), int(cube_m), int(bool(merge)),
-                   float(j_bg), int(orient), int(orient_seed))
+                   float(j_bg), int(orient), int(orient_seed), int(bool(alpha_table)))
 
 
 class Tree:
@@ -195,6 +197,18 @@ def cube_table(n_side, M=None):
     M = DEFAULT_CUBE_PER_NSIDE * n_side if M is None else M
     out = np.zeros(6 * M * M, np.int32)
     lib().or_cube_table(int(n_side), int(M), _p(out))
+    return out
+
+
+A_NCLASS, A_WIDTH = 15, 9
+
+
+def alpha_table(n_side, M=None):
+    """Tabulated angular kernel [6 M M, 15, 9] (pixels 0..3, counts 0..3 of 64, flag)."""
+    M = DEFAULT_CUBE_PER_NSIDE * n_side if M is None else M
+    pix = cube_table(n_side, M)
+    out = np.zeros((6 * M * M, A_NCLASS, A_WIDTH), np.int32)
+    lib().or_alpha_table(int(M), _p(pix), _p(out))
     return out
 
 

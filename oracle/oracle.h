@@ -47,6 +47,9 @@ void or_pix2vec(int n_side, int pix, double *v);
 int or_vec2pix(int n_side, double x, double y, double z);
 /* direction-cell table for the angular kernel: [6][M][M] pixel ids */
 void or_cube_table(int n_side, int M, int32_t *out);
+/* tabulated angular kernel: [6][M][M][15 distance classes][9] = pixels 0..3, counts 0..3
+ * (out of 64), flag of keys reaching more than 4 pixels */
+void or_alpha_table(int M, const int32_t *pixtab, int32_t *out);
 
 typedef struct {
     int n_side;
@@ -57,6 +60,7 @@ typedef struct {
     int orient;                 /* ray-set orientation: 0..47 (signed axis permutation
                                    applied to node offsets), -1 = drawn per target cell */
     unsigned int orient_seed;   /* seed of the per-target draw */
+    int alpha_table;            /* 1: tabulated angular kernel for nodes >= 8 edges away */
 } or_params;
 
 /* Trace every target in `cells` (cell indices; NULL = all n cells, in cell order).

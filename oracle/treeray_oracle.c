@@ -508,6 +508,66 @@ static int cube_cell(const int64_t *d, int M) {
     return (int)((f * M + i) * M + j);
 }
 
+/* Tabulated angular kernel (Sec. 4.2.1: alpha is tabulated over discrete angles and
+ * distances).  For a node at least 8 edges away (r / s >= 8) alpha depends on its direction
+ * cell and its distance class c = floor(log2(r^2 / s^2)), c = 6 .. 20 (the last class
+ * takes everything farther).  The entry of (cell, c) is the share per pixel of the 4^3
+ * stratified sub-points of a cube of edge s_c = |d| 2^(-(c + 1/2)/2) centred on the cell's
+ * centre direction d, each binned to its direction cell and that cell's pixel.  In exact
+ * integers: d = K (2i + 1 - M, 2j + 1 - M, +-M) on the face (K = 2^16), s_c rounded to a
+ * multiple of 8 so that the sub-point offsets (2k - 3) s_c / 8 are integers.  Entries
+ * hold up to 4 pixels (ascending) with their counts out of 64; a key whose sub-points
+ * reach more pixels is marked and its nodes take the per-node kernel. */
+#define A_NSUB 4
+#define A_CFAR 6
+#define A_CMAX 20
+#define A_NCLASS (A_CMAX - A_CFAR + 1)
+#define A_WIDTH 9 /* pixel 0..3, count 0..3, more-than-4 flag */
+
+static int cube_cell(const int64_t *d, int M);
+
+void or_alpha_table(int M, const int32_t *pixtab, int32_t *out) {
+    const int64_t K = (int64_t)1 << 16;
+    for (int f = 0; f < 6; ++f) {
+        int ax = f / 2;
+        int oa = ax == 0 ? 1 : 0, ob = ax == 2 ? 1 : 2;
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                int64_t d[3];
+                d[ax] = (f & 1) ? -(int64_t)M * K : (int64_t)M * K;
+                d[oa] = K * (2 * i + 1 - M);
+                d[ob] = K * (2 * j + 1 - M);
+                double len = sqrt((double)d[0] * d[0] + (double)d[1] * d[1] + (double)d[2] * d[2]);
+                for (int c = A_CFAR; c <= A_CMAX; ++c) {
+                    double x = len * 0.8408964152537145 * ((c & 1) ? 0.7071067811865476 : 1.0) * ldexp(1.0, -(c / 2));
+                    int64_t S = 8 * llround(x / 8.0);
+                    int pix[64], cnt[64], np = 0;
+                    for (int q = 0; q < A_NSUB * A_NSUB * A_NSUB; ++q) {
+                        int64_t e[3] = {d[0] + (2 * (q % 4) - 3) * S / 8, d[1] + (2 * ((q / 4) % 4) - 3) * S / 8,
+                                        d[2] + (2 * (q / 16) - 3) * S / 8};
+                        int px = pixtab[cube_cell(e, M)], k;
+                        for (k = 0; k < np; ++k)
+                            if (pix[k] == px) break;
+                        if (k == np) { pix[np] = px; cnt[np] = 0; ++np; }
+                        cnt[k]++;
+                    }
+                    /* ascending pixel order */
+                    for (int a = 1; a < np; ++a)
+                        for (int b = a; b > 0 && pix[b - 1] > pix[b]; --b) {
+                            int tp = pix[b]; pix[b] = pix[b - 1]; pix[b - 1] = tp;
+                            int tc = cnt[b]; cnt[b] = cnt[b - 1]; cnt[b - 1] = tc;
+                        }
+                    int32_t *o = out + (((int64_t)(f * M + i) * M + j) * A_NCLASS + (c - A_CFAR)) * A_WIDTH;
+                    for (int k = 0; k < 4; ++k) {
+                        o[k] = k < np && np <= 4 ? pix[k] : 0;
+                        o[4 + k] = k < np && np <= 4 ? cnt[k] : 0;
+                    }
+                    o[8] = np > 4;
+                }
+            }
+    }
+}
+
 /* ------------------------------------------------------------------------------------
  * Ray mapping (Sec. 4.2) and integration (Sec. 4.3)
  * ---------------------------------------------------------------------------------- */
@@ -517,6 +577,7 @@ typedef struct {
     const or_tree *t;
     const or_params *p;
     const int32_t *table;
+    const int32_t *alpha; /* tabulated kernel, NULL = per-node kernel only */
     int npix, nbins;
     int64_t c[3], c256[3];
     int64_t target;
@@ -552,11 +613,25 @@ static void map_node(walk_ctx *w, int64_t id) {
     /* radial kernel: beta = R_i^2 / r^2 keeps inverse-square quantities conserved */
     double Ri2fx = (double)((int64_t)FX * i * i) * (double)((int64_t)FX * i * i);
     double beta = Ri2fx / (double)r2;
-    /* angular kernel: 2x2x2 stratified sub-points of the node cube around its mapping
-     * position, each binned to a direction cell and its pixel; alpha = share per pixel */
+    /* angular kernel.  Nodes at least 8 edges away: the tabulated kernel of their
+     * direction cell and distance class.  Nearer nodes (and table keys reaching more than 4
+     * pixels): 2x2x2 stratified sub-points of the node cube around its mapping position,
+     * each binned to a direction cell and its pixel; alpha = share per pixel */
     int64_t h = 64 * t->edge[id]; /* a quarter edge in 1/FX units */
     int pix[8], n_pix = 0, cnt[8];
-    for (int q = 0; q < 8; ++q) {
+    double denom = 8.0;
+    const int64_t s2 = ((int64_t)FX * t->edge[id]) * ((int64_t)FX * t->edge[id]);
+    if (w->alpha && r2 >= 64 * s2) {
+        int c = A_CFAR;
+        while (c < A_CMAX && (s2 << (c + 1)) <= r2) ++c;
+        const int32_t *e = w->alpha + ((int64_t)cube_cell(dl, w->p->cube_m) * A_NCLASS + (c - A_CFAR)) * A_WIDTH;
+        if (!e[8]) {
+            for (int k = 0; k < 4; ++k)
+                if (e[4 + k] > 0) { pix[n_pix] = e[k]; cnt[n_pix] = e[4 + k]; ++n_pix; }
+            denom = 64.0;
+        }
+    }
+    for (int q = 0; q < 8 && denom == 8.0; ++q) {
         int64_t d[3] = {dl[0] + ((q & 1) ? h : -h), dl[1] + ((q & 2) ? h : -h), dl[2] + ((q & 4) ? h : -h)};
         int px = w->table[cube_cell(d, w->p->cube_m)];
         int k;
@@ -577,7 +652,7 @@ static void map_node(walk_ctx *w, int64_t id) {
     }
     int stride = (w->nbins + 1);
     for (int k = 0; k < n_pix; ++k) {
-        double al = cnt[k] / 8.0;
+        double al = cnt[k] / denom;
         double *b = w->bins + ((int64_t)pix[k] * stride + i) * NB_FIELDS;
         b[B_LT] += al * beta * t->Lt[id];
         b[B_AT] += al * beta * t->At[id];
@@ -690,7 +765,7 @@ static void orientation(const or_params *p, int64_t cell, int *perm, int *sgn) {
 }
 
 static int trace_target(const or_tree *t, const or_params *p, const int32_t *table,
-                        const double *dirs, int64_t cell, int brute, double *bins,
+                        const int32_t *alpha, const double *dirs, int64_t cell, int brute, double *bins,
                         uint8_t *flags, double *Fh_out, double *tau_out, double *J,
                         double *F, int64_t *counters) {
     const int npix = 12 * p->n_side * p->n_side;
@@ -698,7 +773,7 @@ static int trace_target(const or_tree *t, const or_params *p, const int32_t *tab
     const int stride = nbins + 1;
     walk_ctx w;
     memset(&w, 0, sizeof(w));
-    w.t = t; w.p = p; w.table = table; w.npix = npix; w.nbins = nbins;
+    w.t = t; w.p = p; w.table = table; w.alpha = alpha; w.npix = npix; w.nbins = nbins;
     w.target = t->node_of_cell[cell];
     orientation(p, cell, w.perm, w.sgn);
     for (int a = 0; a < 3; ++a) {
@@ -752,6 +827,14 @@ static int check_params(const or_tree *t, const or_params *p) {
     return 0;
 }
 
+static int32_t *alpha_for(const or_params *p, const int32_t *table) {
+    if (!p->alpha_table) return NULL;
+    const int M = p->cube_m;
+    int32_t *a = (int32_t *)malloc(sizeof(int32_t) * (size_t)6 * M * M * A_NCLASS * A_WIDTH);
+    or_alpha_table(M, table, a);
+    return a;
+}
+
 int or_trace(const or_tree *t, const or_params *p, int64_t n, const int64_t *cells,
              double *J, double *F, int64_t *counters, int n_threads) {
     if (check_params(t, p)) return -1;
@@ -760,6 +843,7 @@ int or_trace(const or_tree *t, const or_params *p, int64_t n, const int64_t *cel
     int32_t *table = (int32_t *)malloc(sizeof(int32_t) * 6 * (size_t)p->cube_m * p->cube_m);
     double *dirs = (double *)malloc(sizeof(double) * 3 * npix);
     or_cube_table(p->n_side, p->cube_m, table);
+    int32_t *alpha = alpha_for(p, table);
     for (int h = 0; h < npix; ++h) or_pix2vec(p->n_side, h, dirs + 3 * h);
     int err = 0;
 #ifdef _OPENMP
@@ -773,12 +857,12 @@ int or_trace(const or_tree *t, const or_params *p, int64_t n, const int64_t *cel
         for (int64_t k = 0; k < n; ++k) {
             int64_t cell = cells ? cells[k] : k;
             if (cell < 0 || cell >= t->n_cells) { err = -1; continue; }
-            trace_target(t, p, table, dirs, cell, 0, bins, flags, NULL, NULL,
+            trace_target(t, p, table, alpha, dirs, cell, 0, bins, flags, NULL, NULL,
                          J ? J + k : NULL, F ? F + 3 * k : NULL, counters ? counters + 3 * k : NULL);
         }
         free(bins); free(flags);
     }
-    free(table); free(dirs);
+    free(table); free(alpha); free(dirs);
     return err;
 }
 
@@ -789,9 +873,10 @@ int or_trace_one(const or_tree *t, const or_params *p, int64_t cell, int brute, 
     int32_t *table = (int32_t *)malloc(sizeof(int32_t) * 6 * (size_t)p->cube_m * p->cube_m);
     double *dirs = (double *)malloc(sizeof(double) * 3 * npix);
     or_cube_table(p->n_side, p->cube_m, table);
+    int32_t *alpha = alpha_for(p, table);
     for (int h = 0; h < npix; ++h) or_pix2vec(p->n_side, h, dirs + 3 * h);
-    trace_target(t, p, table, dirs, cell, brute, bins, flags, Fh, tau_thin_tot, J, F, NULL);
-    free(table); free(dirs);
+    trace_target(t, p, table, alpha, dirs, cell, brute, bins, flags, Fh, tau_thin_tot, J, F, NULL);
+    free(table); free(alpha); free(dirs);
     return 0;
 }
 

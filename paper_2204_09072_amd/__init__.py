@@ -50,7 +50,8 @@ class TraceParams(C.Structure):
     _fields_ = [("n_side", C.c_int32), ("theta_num", C.c_int32), ("theta_den", C.c_int32),
                 ("cube_m", C.c_int32), ("merge", C.c_int32), ("j_bg", C.c_float),
                 ("bins_per_pass", C.c_int32), ("chunk", C.c_int32), ("waves_per_block", C.c_int32),
-                ("kernel", C.c_int32), ("orientation", C.c_int32), ("orient_seed", C.c_uint32)]
+                ("kernel", C.c_int32), ("per_node_kernel", C.c_int32), ("orientation", C.c_int32),
+                ("orient_seed", C.c_uint32)]
 
 
 class BatchTuning(C.Structure):
@@ -94,6 +95,7 @@ _sig("tr_batch_tune", _I, [_P, _I, C.POINTER(BatchTuning)])
 _sig("tr_batch_free", None, [_P])
 _sig("tr_trace_rays_batched", _I, [_P, _I, _P, _P, _P, _P, _P])
 _sig("tr_ray_tables", _I, [_P, _I, _I, _P, _P])
+_sig("tr_alpha_table", _I, [_P, _I, _I, _P])
 _sig("tr_rad_force", _I, [_P, _P, _P, _P, _P])
 _sig("tr_dust_fixed_point", _I, [_P, C.POINTER(Grid), _P, _P, _P, _I, C.POINTER(Units), C.POINTER(TraceParams),
                                   C.POINTER(DustParams), _P, _I, C.c_float, _P, _P, _P, _P,
@@ -246,13 +248,15 @@ def tree_export(ctx: Context, tree: Tree):
 
 
 def trace_params(n_side, theta=None, cube_m=0, merge=True, j_bg=0.0, bins_per_pass=0, chunk=0,
-                 waves_per_block=0, kernel=0, orientation=0, orient_seed=0) -> TraceParams:
+                 waves_per_block=0, kernel=0, per_node_kernel=False, orientation=0,
+                 orient_seed=0) -> TraceParams:
     """kernel: 0 automatic, 1 one wave per target, 2 one block per target.
+    per_node_kernel: the 8-point kernel for every node instead of the table for far ones.
     orientation: 0..47 signed axis permutation of the ray set, -1 drawn per target."""
     th = (0, 0) if theta is None else theta
     return TraceParams(int(n_side), int(th[0]), int(th[1]), int(cube_m), int(bool(merge)),
                        float(j_bg), int(bins_per_pass), int(chunk), int(waves_per_block), int(kernel),
-                       int(orientation), int(orient_seed))
+                       int(bool(per_node_kernel)), int(orientation), int(orient_seed))
 
 
 def trace_rays(ctx: Context, tree: Tree, p: TraceParams, J, F, u_rad=None):
@@ -320,6 +324,14 @@ def ray_tables(ctx: Context, n_side: int, cube_m: int = 0):
     dirs = np.zeros((12 * n_side * n_side, 3), np.float32)
     ctx.check(_lib.tr_ray_tables(ctx.h, int(n_side), int(M), _ptr(tab), _ptr(dirs)))
     return tab, dirs
+
+
+def alpha_table(ctx: Context, n_side: int, cube_m: int = 0):
+    """tr_alpha_table: host int32 [6 M M, 15, 9]."""
+    M = cube_m or 16 * n_side
+    out = np.zeros((6 * M * M, 15, 9), np.int32)
+    ctx.check(_lib.tr_alpha_table(ctx.h, int(n_side), int(M), _ptr(out)))
+    return out
 
 
 def rad_force(ctx: Context, tree: Tree, F, a_rp, p_src=None):

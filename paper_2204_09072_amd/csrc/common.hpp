@@ -18,10 +18,9 @@ struct RayTable {
     int n_side = 0, cube_m = 0;
     int16_t *table = nullptr; // [6][M][M] pixel ids
     float4 *dirs = nullptr;   // [npix] unit vectors
-    // [6][M][M] 4-bit entries, two per byte (even cell in the low nibble): side of the
-    // largest square of direction cells starting at the cell (towards larger i and j on
-    // its face) that lies in one pixel, capped at 15
-    uint8_t *square = nullptr;
+    // tabulated angular kernel: [6][M][M][15 distance classes] int4 entries (pixels 0-1,
+    // pixels 2-3, counts of 64, more-than-4-pixels flag)
+    int4 *alpha = nullptr;
 };
 
 struct tr_ctx {

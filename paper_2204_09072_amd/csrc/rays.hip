@@ -3,7 +3,9 @@
 // Rays are the HEALPix pixels (Gorski et al. 2005, NESTED numbering).  The angular
 // kernel maps a direction to its pixel through a table over discrete directions: the
 // six faces of a cube split into M x M cells, each cell holding the pixel of its centre
-// direction.  Both tables are built once per (N_side, M) on the device in FP64.
+// direction.  Both tables are built once per (N_side, M) on the device in FP64; the
+// tabulated angular kernel of distant nodes follows from the pixel table on the host.
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -137,9 +139,11 @@ int tr_get_table(tr_ctx *ctx, int n_side, int cube_m, RayTable **out) {
         hipFree(rt.dirs);
         return tr_fail(ctx, TR_EHIP, "table kernels failed to launch");
     }
-    // Uniform squares of direction cells, found on the host from the pixel table:
-    // side(i, j) = 1 + min(side(i+1, j), side(i, j+1), side(i+1, j+1)) when the 2x2 cells at
-    // (i, j) share one pixel, else 1 (the classic largest-square recurrence).
+    // Tabulated angular kernel (Sec. 4.2.1), built on the host from the pixel table in exact
+    // integers: for direction cell (f, i, j) with centre d = K (2i + 1 - M, 2j + 1 - M, +-M)
+    // on its face (K = 2^16) and distance class c = 6 .. 20, the 4^3 stratified sub-points
+    // of a cube of edge s_c = |d| 2^(-(c + 1/2)/2) (rounded to a multiple of 8) centred on
+    // d, each binned to its direction cell and that cell's pixel.
     std::vector<int16_t> pix(ne);
     if (hipMemcpyAsync(pix.data(), rt.table, sizeof(int16_t) * ne, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -148,29 +152,67 @@ int tr_get_table(tr_ctx *ctx, int n_side, int cube_m, RayTable **out) {
         return tr_fail(ctx, TR_EHIP, "direction-cell table readback failed");
     }
     const int M = cube_m;
-    std::vector<uint8_t> side(ne), nib((ne + 1) / 2, 0);
-    for (int f = 0; f < 6; ++f)
-        for (int i = M - 1; i >= 0; --i)
-            for (int j = M - 1; j >= 0; --j) {
-                const int64_t e = ((int64_t)f * M + i) * M + j;
-                int v = 1;
-                if (i + 1 < M && j + 1 < M) {
-                    const int64_t ei = e + M, ej = e + 1, eij = e + M + 1;
-                    if (pix[e] == pix[ei] && pix[e] == pix[ej] && pix[e] == pix[eij]) {
-                        int m = side[ei] < side[ej] ? side[ei] : side[ej];
-                        m = m < side[eij] ? m : side[eij];
-                        v = 1 + m;
+    const int64_t K = (int64_t)1 << 16;
+    auto cell_of = [&](const int64_t *d) {
+        const int64_t a0 = d[0] < 0 ? -d[0] : d[0], a1 = d[1] < 0 ? -d[1] : d[1], a2 = d[2] < 0 ? -d[2] : d[2];
+        const int ax = (a0 >= a1 && a0 >= a2) ? 0 : (a1 >= a2 ? 1 : 2);
+        const int oa = ax == 0 ? 1 : 0, ob = ax == 2 ? 1 : 2;
+        const int64_t m = ax == 0 ? a0 : (ax == 1 ? a1 : a2);
+        const int f = 2 * ax + (d[ax] < 0 ? 1 : 0);
+        int64_t i = ((int64_t)M * (d[oa] + m)) / (2 * m), j = ((int64_t)M * (d[ob] + m)) / (2 * m);
+        i = i > M - 1 ? M - 1 : i;
+        j = j > M - 1 ? M - 1 : j;
+        return (int64_t)(f * M + i) * M + j;
+    };
+    constexpr int nclass = 15;
+    std::vector<int4> alpha(ne * nclass);
+    for (int f = 0; f < 6; ++f) {
+        const int ax = f / 2, oa = ax == 0 ? 1 : 0, ob = ax == 2 ? 1 : 2;
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                int64_t d[3];
+                d[ax] = (f & 1) ? -(int64_t)M * K : (int64_t)M * K;
+                d[oa] = K * (2 * i + 1 - M);
+                d[ob] = K * (2 * j + 1 - M);
+                const double len = std::sqrt((double)d[0] * d[0] + (double)d[1] * d[1] + (double)d[2] * d[2]);
+                for (int c = 6; c <= 20; ++c) {
+                    const double x = len * 0.8408964152537145 * ((c & 1) ? 0.7071067811865476 : 1.0) *
+                                     std::ldexp(1.0, -(c / 2));
+                    const int64_t S = 8 * std::llround(x / 8.0);
+                    int px[64], cnt[64], np = 0;
+                    for (int q = 0; q < 64; ++q) {
+                        const int64_t e[3] = {d[0] + (2 * (q % 4) - 3) * S / 8, d[1] + (2 * ((q / 4) % 4) - 3) * S / 8,
+                                              d[2] + (2 * (q / 16) - 3) * S / 8};
+                        const int p = pix[cell_of(e)];
+                        int k = 0;
+                        while (k < np && px[k] != p) ++k;
+                        if (k == np) { px[np] = p; cnt[np] = 0; ++np; }
+                        cnt[k]++;
                     }
+                    for (int u = 1; u < np; ++u)
+                        for (int v = u; v > 0 && px[v - 1] > px[v]; --v) {
+                            std::swap(px[v], px[v - 1]);
+                            std::swap(cnt[v], cnt[v - 1]);
+                        }
+                    int4 en = make_int4(0, 0, 0, np > 4 ? 1 : 0);
+                    if (np <= 4) {
+                        int pp[4] = {0, 0, 0, 0}, cc[4] = {0, 0, 0, 0};
+                        for (int k = 0; k < np; ++k) { pp[k] = px[k]; cc[k] = cnt[k]; }
+                        en.x = (int)((uint32_t)pp[0] | ((uint32_t)pp[1] << 16));
+                        en.y = (int)((uint32_t)pp[2] | ((uint32_t)pp[3] << 16));
+                        en.z = (int)((uint32_t)cc[0] | ((uint32_t)cc[1] << 8) | ((uint32_t)cc[2] << 16) |
+                                     ((uint32_t)cc[3] << 24));
+                    }
+                    alpha[(((int64_t)f * M + i) * M + j) * nclass + (c - 6)] = en;
                 }
-                side[e] = (uint8_t)(v > 15 ? 15 : v);
             }
-    for (int64_t e = 0; e < ne; ++e) nib[e >> 1] |= (uint8_t)(side[e] << (4 * (e & 1)));
-    if (hipMalloc(&rt.square, nib.size()) != hipSuccess ||
-        hipMemcpy(rt.square, nib.data(), nib.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    }
+    if (hipMalloc(&rt.alpha, sizeof(int4) * alpha.size()) != hipSuccess ||
+        hipMemcpy(rt.alpha, alpha.data(), sizeof(int4) * alpha.size(), hipMemcpyHostToDevice) != hipSuccess) {
         hipFree(rt.table);
         hipFree(rt.dirs);
-        hipFree(rt.square);
-        return tr_fail(ctx, TR_ENOMEM, "uniform-square table");
+        hipFree(rt.alpha);
+        return tr_fail(ctx, TR_ENOMEM, "tabulated angular kernel");
     }
     ctx->tables[key] = rt;
     *out = &ctx->tables[key];
@@ -196,6 +238,28 @@ extern "C" int tr_ray_tables(tr_ctx *ctx, int n_side, int cube_m, int32_t *table
         dirs[3 * p] = d4[p].x;
         dirs[3 * p + 1] = d4[p].y;
         dirs[3 * p + 2] = d4[p].z;
+    }
+    return TR_OK;
+}
+
+extern "C" int tr_alpha_table(tr_ctx *ctx, int n_side, int cube_m, int32_t *out) {
+    if (!ctx) return TR_EINVAL;
+    if (!out) return tr_fail(ctx, TR_EINVAL, "tr_alpha_table: null output");
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    if (cube_m == 0) cube_m = 16 * n_side;
+    RayTable *rt = nullptr;
+    int rc = tr_get_table(ctx, n_side, cube_m, &rt);
+    if (rc) return rc;
+    const int64_t nk = 6 * (int64_t)cube_m * cube_m * 15;
+    std::vector<int4> a(nk);
+    TR_HIP(ctx, hipMemcpyAsync(a.data(), rt->alpha, sizeof(int4) * nk, hipMemcpyDeviceToHost, ctx->stream));
+    TR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t k = 0; k < nk; ++k) {
+        int32_t *o = out + 9 * k;
+        o[0] = a[k].x & 0xffff; o[1] = (int32_t)((uint32_t)a[k].x >> 16);
+        o[2] = a[k].y & 0xffff; o[3] = (int32_t)((uint32_t)a[k].y >> 16);
+        for (int c = 0; c < 4; ++c) o[4 + c] = (int32_t)(((uint32_t)a[k].z >> (8 * c)) & 255u);
+        o[8] = a[k].w;
     }
     return TR_OK;
 }

@@ -39,7 +39,7 @@ extern "C" void tr_ctx_destroy(tr_ctx *c) {
     for (auto &kv : c->tables) {
         hipFree(kv.second.table);
         hipFree(kv.second.dirs);
-        hipFree(kv.second.square);
+        hipFree(kv.second.alpha);
     }
     hipFree(c->d_ctl);
     hipFree(c->ws_guess);

@@ -16,19 +16,19 @@
 // opening test, the pruning test and the radial bin search are exact integer
 // comparisons; the bin search takes a float estimate and falls back to 64-bit integers
 // only within rounding distance of a bin edge.  Accepted nodes that touch the pass are
-// compacted into one of two LDS queues and mapped 64 at a time, so the 8-point angular
-// kernel runs with every lane busy on the same code path: nodes whose eight sub-points
-// all fall on one cube face take a short path (two reciprocals for the eight points,
-// and a single pixel when the points' direction cells lie inside one uniform square of
-// the pixel table), the rest the general one.  A block holds several such waves; they
-// share one copy of the direction-cell tables in LDS when the pixel ids fit a byte.
+// compacted into one of two LDS queues and mapped 64 at a time, so the angular kernel runs
+// with every lane busy on the same code path: nodes at least 8 edges away take the
+// tabulated kernel (one direction cell and one table load per node), nearer ones the
+// per-node 8-point kernel.  A block holds several such waves; they share one copy of the
+// direction-cell table in LDS when the pixel ids fit a byte.
 #include "common.hpp"
 
 namespace {
 
 constexpr float kPiF = 3.14159265358979f;
-// accepted nodes waiting to be mapped: the one-face queue grows up from 0, the general one
-// down from kQueue - 1; each holds < 64 entries before a walk step adds at most 64
+// accepted nodes waiting to be mapped: the far-node queue (tabulated kernel) grows up from
+// 0, the near-node one down from kQueue - 1; each holds < 64 entries before a walk step
+// adds at most 64
 constexpr int kQueue = 192;
 constexpr int kFields = 6;  // L_thin, A_thin, L_thick*V, A_thick, V_thick, Q
 constexpr int kThin = 2;    // fields held in LDS: L_thin, A_thin
@@ -47,7 +47,7 @@ struct TraceArgs {
     const float *cell_tau;
     const float *cell_src;
     const int16_t *table;
-    const uint8_t *square; // uniform-square sides, 4 bits per direction cell
+    const int4 *alpha;     // tabulated angular kernel [6 M M][distance classes]
     const float4 *dirs;
     int *work;
     int *err;
@@ -74,6 +74,7 @@ struct TraceArgs {
     int fcap;       // cooperative kernel: frontier capacity (child ranges per depth)
     int tab_slot;   // batched launches: which LDS table set the instance uses
     int orient;     // ray-set orientation 0..47, -1 = drawn per target
+    int per_node;   // 1: the per-node angular kernel for every node (no table)
     uint32_t orient_seed;
     int per_block;  // waves per block
     int lds_wave;   // bytes of LDS per wave
@@ -174,16 +175,6 @@ __device__ __forceinline__ void cswap(int &a, int &b) {
     b = hi;
 }
 
-// True when the eight sub-points d + (+-h, +-h, +-h) of a node all have the largest
-// component on the axis (and with the sign) of the centre offset d, with cube_cell's
-// tie rule: then they share one cube face.
-__device__ __forceinline__ bool one_face(int dx, int dy, int dz, int h) {
-    const int ax = abs(dx), ay = abs(dy), az = abs(dz), h2 = 2 * h;
-    if (ax >= ay && ax >= az) return ax - h2 >= max(ay, az);
-    if (ay >= az) return ay - h2 > ax && ay - h2 >= az;
-    return az - h2 > max(ax, ay);
-}
-
 // Orientation of the ray set (Sec. 7.6 names different HEALPix orientations as the remedy
 // for ray artefacts): one of the 48 signed permutations of the axes, which map the lattice
 // onto itself.  Index o: axis permutation o / 8 in the order 012 021 102 120 201 210, sign
@@ -230,29 +221,70 @@ __device__ __forceinline__ void orient_back(int o, float &fx, float &fy, float &
     fz = p0 == 2 ? f0 : (p1 == 2 ? f1 : f2);
 }
 
+// lane-shifted copies within rows of 16 lanes (DPP row_shr / row_shl); lanes whose source
+// lies outside the row receive `old`
+template <int N>
+__device__ __forceinline__ int dpp_shr(int v, int old) {
+    return __builtin_amdgcn_update_dpp(old, v, 0x110 | N, 0xf, 0xf, false);
+}
+template <int N>
+__device__ __forceinline__ int dpp_shl(int v, int old) {
+    return __builtin_amdgcn_update_dpp(old, v, 0x100 | N, 0xf, 0xf, false);
+}
+template <int N>
+__device__ __forceinline__ float dpp_shr_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 | N, 0xf, 0xf, false));
+}
+
+// one step of a segmented inclusive sum over runs of equal run ids inside a row of 16
+template <int D>
+__device__ __forceinline__ void seg_sum_step(int rl, int rid, float &v0, float &v1) {
+    const int r = dpp_shr<D>(rid, -1);
+    const float a0 = dpp_shr_f<D>(v0), a1 = dpp_shr_f<D>(v1);
+    if (rl >= D && r == rid) {
+        v0 += a0;
+        v1 += a1;
+    }
+}
+
+// Tabulated angular kernel (Sec. 4.2.1): nodes at least 8 edges away (r >= 8 s) take the
+// entry of their direction cell and distance class c = floor(log2(r^2 / s^2)), 6 <= c <= 20
+// (larger classes count as 20).  Entry int4: pixels 0, 1 (x, 16 bits each), pixels 2, 3
+// (y), the four counts out of 64 (z, 8 bits each), and w != 0 when the key's sub-points
+// reach more than 4 pixels (the node then takes the per-node kernel).
+constexpr int kAlphaFar = 6;
+constexpr int kAlphaMax = 20;
+constexpr int kAlphaClasses = kAlphaMax - kAlphaFar + 1;
+
+// a node is served by the table when r^2 >= 64 s^2 (all in 1/256 lattice units)
+__device__ __forceinline__ bool far_node(int dx, int dy, int dz, int s) {
+    const int64_t r2 = (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz;
+    const int64_t sf = (int64_t)TR_FX * s;
+    return r2 >= 64 * sf * sf;
+}
+
 // Queue record of an accepted node: pk = content segment (i - a + 1, 0 = none) | first
 // merge flag << 6 | end of merge flags << 12 (both relative to the pass) | leaf << 18 |
 // depth << 19.
 //
-// Map queued nodes (Sec. 4.2.1/4.2.2): one lane per node, the angular kernel from the node
-// cube's 2x2x2 sub-points, one LDS update per distinct pixel.  ONE_FACE: every node of the
-// batch has its sub-points on one cube face (one_face), so the eight direction cells are
-// (i(a, m), j(b, m)) for the two minor offsets a, b = centre +- h and the two major
-// magnitudes m = |centre| -+ h: four quotients per minor axis instead of eight, and when
-// the cells' bounding square lies inside one uniform square of the table the node maps
-// whole to one pixel.
-// SPLIT: merge flags in flg and thick-content flags in flgt, one bit per segment of the pass
-// each (passes of up to 31 segments); otherwise both in flg (thick bits from bit 16).
-template <bool LDS_TABLE, bool ONE_FACE, bool SPLIT = false>
+// Map queued nodes (Sec. 4.2.1/4.2.2): one lane per node, one LDS update per distinct pixel.
+// FAR: every node of the batch is at least 8 edges away and takes the tabulated kernel (one
+// direction cell, one table load); otherwise the per-node kernel: the node cube's 2x2x2
+// sub-points, each binned to a direction cell and its pixel, sorted to find the distinct
+// pixels.  SPLIT: merge flags in flg and thick-content flags in flgt, one bit per segment
+// of the pass each (passes of up to 31 segments); otherwise both in flg (thick bits from
+// bit 16).
+template <bool LDS_TABLE, bool FAR, bool SPLIT = false>
 __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *qnode, const uint32_t *qpk,
-                                          int pass_a, int4 c256, int orient, const uint8_t *tab8,
-                                          const uint8_t *sqt, float *bins, uint32_t *flg, float4 *thick,
-                                          uint32_t *flgt = nullptr) {
+                                          int pass_a, int4 c256, int orient, const uint8_t *tab8, float *bins,
+                                          uint32_t *flg, float4 *thick, uint32_t *flgt = nullptr) {
     uint32_t starts = 0;
     int pix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     float Lt = 0, At = 0, LVk = 0, Ak = 0, Vk = 0, beta = 0;
     int seg = -1;
     uint32_t fbits = 0;
+    uint32_t counts = 0; // tabulated entries: counts out of 64 of pix[0..3]
+    bool tab = false;
     if (e >= 0) {
         const int node = qnode[e];
         const uint32_t pk = qpk[e];
@@ -284,58 +316,31 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             beta = (R2 * R2) * rcp(fx * fx + fy * fy + fz * fz);
         }
         orient_offset(orient, dx, dy, dz); // the angular kernel works in the ray set's frame
-        const int h = (TR_FX / 4) * s;
         auto lookup = [&](int cell) { return LDS_TABLE ? (int)tab8[cell] : (int)A.table[cell]; };
-        bool single = false;
-        if (ONE_FACE) {
-            const int ax = abs(dx), ay = abs(dy), az = abs(dz);
-            int f, dm, da, db;
-            if (ax >= ay && ax >= az) {
-                f = dx < 0 ? 1 : 0; dm = ax; da = dy; db = dz;
-            } else if (ay >= az) {
-                f = dy < 0 ? 3 : 2; dm = ay; da = dx; db = dz;
-            } else {
-                f = dz < 0 ? 5 : 4; dm = az; da = dx; db = dy;
+        if (FAR) {
+            // distance class: c = floor(log2(r^2 / s^2)) from the leading bits, corrected once
+            const int64_t r2 = (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz;
+            const int64_t sf = (int64_t)TR_FX * s, s2 = sf * sf;
+            int c = (63 - __clzll(r2)) - (63 - __clzll(s2));
+            if ((s2 << c) > r2) --c;
+            c = c > kAlphaMax ? kAlphaMax : c;
+            const int4 en = A.alpha[cube_cell(dx, dy, dz, A.log2m) * kAlphaClasses + (c - kAlphaFar)];
+            if (en.w == 0) {
+                tab = true;
+                pix[0] = en.x & 0xffff;
+                pix[1] = (int)((uint32_t)en.x >> 16);
+                pix[2] = en.y & 0xffff;
+                pix[3] = (int)((uint32_t)en.y >> 16);
+                counts = (uint32_t)en.z;
             }
-            const int m1 = dm - h, m2 = dm + h;
-            const uint32_t n1 = 2u * (uint32_t)m1, n2 = 2u * (uint32_t)m2;
-            const float r1 = rcp((float)n1), r2 = rcp((float)n2);
-            const uint32_t Mm1 = (1u << A.log2m) - 1u;
-            auto q = [&](int a, int m, uint32_t den, float rc) {
-                const uint32_t v = exact_div((uint32_t)(a + m) << A.log2m, den, rc);
-                return v > Mm1 ? Mm1 : v;
-            };
-            const uint32_t ia1 = q(da - h, m1, n1, r1), ib1 = q(da + h, m1, n1, r1);
-            const uint32_t ia2 = q(da - h, m2, n2, r2), ib2 = q(da + h, m2, n2, r2);
-            const uint32_t ja1 = q(db - h, m1, n1, r1), jb1 = q(db + h, m1, n1, r1);
-            const uint32_t ja2 = q(db - h, m2, n2, r2), jb2 = q(db + h, m2, n2, r2);
-            const uint32_t i0 = min(ia1, ia2), i1 = max(ib1, ib2), j0 = min(ja1, ja2), j1 = max(jb1, jb2);
-            const int fb = f << A.log2m;
-            const int base = ((fb + (int)i0) << A.log2m) + (int)j0;
-            const uint32_t side = (uint32_t)(sqt[base >> 1] >> (4 * (base & 1))) & 15u;
-            if (side > max(i1 - i0, j1 - j0)) {
-                pix[0] = lookup(base);
-                single = true;
-            } else {
-                pix[0] = lookup(((fb + (int)ia1) << A.log2m) + (int)ja1);
-                pix[1] = lookup(((fb + (int)ia1) << A.log2m) + (int)jb1);
-                pix[2] = lookup(((fb + (int)ib1) << A.log2m) + (int)ja1);
-                pix[3] = lookup(((fb + (int)ib1) << A.log2m) + (int)jb1);
-                pix[4] = lookup(((fb + (int)ia2) << A.log2m) + (int)ja2);
-                pix[5] = lookup(((fb + (int)ia2) << A.log2m) + (int)jb2);
-                pix[6] = lookup(((fb + (int)ib2) << A.log2m) + (int)ja2);
-                pix[7] = lookup(((fb + (int)ib2) << A.log2m) + (int)jb2);
-            }
-        } else {
+        }
+        if (!tab) {
+            const int h = (TR_FX / 4) * s;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int cx = dx + ((k & 1) ? h : -h), cy = dy + ((k & 2) ? h : -h), cz = dz + ((k & 4) ? h : -h);
                 pix[k] = lookup(cube_cell(cx, cy, cz, A.log2m));
             }
-        }
-        if (single) {
-            starts = 1u;
-        } else {
             // sort the 8 pixel ids (19-comparator network), then mark runs of equal ids
             cswap(pix[0], pix[2]); cswap(pix[1], pix[3]); cswap(pix[4], pix[6]); cswap(pix[5], pix[7]);
             cswap(pix[0], pix[4]); cswap(pix[1], pix[5]); cswap(pix[2], pix[6]); cswap(pix[3], pix[7]);
@@ -346,24 +351,39 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             starts = 1u;
 #pragma unroll
             for (int k = 1; k < 8; ++k) starts |= (pix[k] != pix[k - 1] ? 1u : 0u) << k;
+        } else {
+            // one "run" per tabulated pixel with a non-zero count
+#pragma unroll
+            for (int k = 0; k < 4; ++k) starts |= (((counts >> (8 * k)) & 255u) != 0u ? 1u : 0u) << k;
         }
     }
-    // one LDS update per distinct pixel; the loop runs as often as the busiest lane needs
+    // one update per distinct pixel; the loop runs as often as the busiest lane needs.  Thin
+    // contributions are first summed over runs of neighbouring lanes that hit the same
+    // (pixel, segment) -- siblings of one parent usually do -- so that one LDS atomic per
+    // run, not per lane, reaches the bins.
+    const int lane = lane_id(), rl = lane & 15;
     while (__ballot(starts != 0u)) {
+        int key = -1;
+        float v0 = 0.0f, v1 = 0.0f;
         if (starts) {
             const int k = __builtin_ctz(starts);
             starts &= starts - 1u;
-            const int kn = starts ? __builtin_ctz(starts) : 8;
             int px = pix[0];
 #pragma unroll
             for (int j = 1; j < 8; ++j) px = k == j ? pix[j] : px;
-            const float al = 0.125f * (float)(kn - k);
+            float al;
+            if (FAR && tab) {
+                al = (1.0f / 64.0f) * (float)((counts >> (8 * k)) & 255u);
+            } else {
+                const int kn = starts ? __builtin_ctz(starts) : 8;
+                al = 0.125f * (float)(kn - k);
+            }
             uint32_t fl = fbits, ft = 0u;
             if (seg >= 0) {
-                float *bb = bins + (px * A.bp + seg) * kThin;
                 const float ab = al * beta;
-                if (Lt != 0.0f) atomicAdd(bb + 0, ab * Lt);
-                if (At != 0.0f) atomicAdd(bb + 1, ab * At);
+                key = px * A.bp + seg;
+                v0 = ab * Lt;
+                v1 = ab * At;
                 if (Vk > 0.0f) {
                     float *tk = reinterpret_cast<float *>(thick + px * A.bp + seg);
                     atomicAdd(tk + 0, al * LVk);
@@ -380,6 +400,22 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
                 fl |= ft << 16;
                 if (fl) atomicOr(flg + px, fl);
             }
+        }
+        // runs of equal keys within rows of 16 lanes (wave-uniform control flow from here):
+        // run id = number of run heads up to this lane, then a segmented inclusive sum
+        const int prev = dpp_shr<1>(key, -2);
+        const bool head = rl == 0 || prev != key;
+        const uint64_t hb = __ballot(head);
+        const int rid = __builtin_popcountll(hb & ((2ull << lane) - 1ull));
+        seg_sum_step<1>(rl, rid, v0, v1);
+        seg_sum_step<2>(rl, rid, v0, v1);
+        seg_sum_step<4>(rl, rid, v0, v1);
+        seg_sum_step<8>(rl, rid, v0, v1);
+        const int nrid = dpp_shl<1>(rid, 0);
+        if (key >= 0 && (rl == 15 || nrid != rid)) {
+            float *bb = bins + key * kThin;
+            if (v0 != 0.0f) atomicAdd(bb + 0, v0);
+            if (v1 != 0.0f) atomicAdd(bb + 1, v1);
         }
     }
 }
@@ -423,7 +459,7 @@ __device__ __forceinline__ void integrate_segment(const float *s, int i, float o
 // better): leaves are accepted, h-nodes accepted when s/d < theta and otherwise opened
 // (their child range is returned in `push` unless the pass prunes the subtree); an
 // accepted node whose material can reach the pass is returned as a queue record (`pk`,
-// and whether its sub-points share one cube face).
+// and whether it is far enough for the tabulated angular kernel).
 struct Target {
     int tid, tx, ty, tz;
     int4 c256;
@@ -437,7 +473,7 @@ struct PassGeo {
 template <bool COUNT>
 __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const Target &T, const PassGeo &G,
                                            int &n_b, int &n_h, int &n_open, bool &open, uint32_t &push,
-                                           bool &enq, uint32_t &pk, bool &face1) {
+                                           bool &enq, uint32_t &pk, bool &far1) {
     const int4 nd = A.nodes[node];
     const int depth = (nd.x >> 16) & 15;
     const bool leaf = (nd.x >> 20) & 1;
@@ -530,9 +566,7 @@ __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const T
                     pk = (content ? (uint32_t)(i - G.a + 1) : 0u) | ((uint32_t)k0 << 6) |
                          ((uint32_t)k1 << 12) | ((leaf ? 1u : 0u) << 18) |
                          ((uint32_t)depth << 19);
-                    int ox = dx, oy = dy, oz = dz;
-                    orient_offset(T.orient, ox, oy, oz);
-                    face1 = one_face(ox, oy, oz, (TR_FX / 4) * s);
+                    far1 = !A.per_node && far_node(dx, dy, dz, s);
                 }
             }
         }
@@ -540,7 +574,7 @@ __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const T
 }
 
 template <int NSLOT, bool COUNT, bool LDS_TABLE>
-__device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_t *tab8, const uint8_t *sqt,
+__device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_t *tab8,
                              float4 *thick) {
     const LdsLayout LL = lds_layout(A.npix, A.bp, A.kstack, COUNT);
     float *bins = reinterpret_cast<float *>(lds + LL.bins);
@@ -578,7 +612,7 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
             for (int k = lane; k < A.npix; k += 64) flg[k] = 0u;
         }
         if (lane == 0) stk[0] = 0u; // the root: first node 0, one node
-        int sp = 1, qf = 0, qs = 0; // stack depth, one-face and general queue lengths
+        int sp = 1, qf = 0, qs = 0; // stack depth, far and near queue lengths
         wave_sync();
         while (sp > 0 || qf > 0 || qs > 0) {
             if (sp > 0) {
@@ -588,7 +622,7 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                 sp -= npop;
                 wave_sync();
                 const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
-                bool open = false, enq = false, face1 = false;
+                bool open = false, enq = false, far1 = false;
                 uint32_t push = 0, pk = 0;
                 if (node >= 0) {
                     const int4 nd = A.nodes[node];
@@ -683,9 +717,7 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                                     pk = (content ? (uint32_t)(i - P.a + 1) : 0u) | ((uint32_t)k0 << 6) |
                                          ((uint32_t)k1 << 12) | ((leaf ? 1u : 0u) << 18) |
                                          ((uint32_t)depth << 19);
-                                    int ox = dx, oy = dy, oz = dz;
-                                    orient_offset(orient, ox, oy, oz);
-                                    face1 = one_face(ox, oy, oz, (TR_FX / 4) * s);
+                                    far1 = !A.per_node && far_node(dx, dy, dz, s);
                                 }
                             }
                         }
@@ -703,9 +735,9 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                     sp += npush;
                 }
                 if (!COUNT) {
-                    const uint64_t fb = __ballot(enq && face1), gb = __ballot(enq && !face1);
+                    const uint64_t fb = __ballot(enq && far1), gb = __ballot(enq && !far1);
                     if (enq) {
-                        const int qp = face1 ? qf + __builtin_popcountll(fb & below)
+                        const int qp = far1 ? qf + __builtin_popcountll(fb & below)
                                              : kQueue - 1 - qs - __builtin_popcountll(gb & below);
                         qnode[qp] = node;
                         qpk[qp] = pk;
@@ -720,14 +752,14 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
             if (qf >= 64 || (sp == 0 && qf > 0)) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = lane < nq ? qf - nq + lane : -1;
-                map_queue<LDS_TABLE, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flg, thick);
+                map_queue<LDS_TABLE, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick);
                 qf -= nq;
                 wave_sync();
             }
             if (qs >= 64 || (sp == 0 && qs > 0)) {
                 const int nq = qs >= 64 ? 64 : qs;
                 const int e = lane < nq ? kQueue - qs + lane : -1;
-                map_queue<LDS_TABLE, false>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flg, thick);
+                map_queue<LDS_TABLE, false>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick);
                 qs -= nq;
                 wave_sync();
             }
@@ -844,12 +876,11 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
     extern __shared__ __align__(16) char smem[];
     const uint8_t *tab8 = reinterpret_cast<const uint8_t *>(smem);
     const int ncell = 6 << (2 * A.log2m);
-    const uint8_t *sqt = A.square;
+
     if (LDS_TABLE) {
         uint8_t *t = reinterpret_cast<uint8_t *>(smem);
         for (int k = threadIdx.x; k < ncell; k += blockDim.x) t[k] = (uint8_t)A.table[k];
-        for (int k = threadIdx.x; k < ncell / 2; k += blockDim.x) t[ncell + k] = A.square[k];
-        sqt = t + ncell;
+
         __syncthreads();
     }
     char *lds = smem + A.lds_table + (threadIdx.x >> 6) * A.lds_wave;
@@ -871,7 +902,7 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
             t0 = __shfl(t0, 0) + lo;
             if (t0 >= hi) break;
             const int t1 = t0 + A.chunk < hi ? t0 + A.chunk : hi;
-            for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE>(A, ti, lds, tab8, sqt, thick);
+            for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE>(A, ti, lds, tab8, thick);
         }
     }
 }
@@ -907,7 +938,7 @@ __host__ __device__ inline CoopLayout coop_layout(int npix, int bp, int fcap, in
 }
 
 __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLayout &L, int fcap,
-                            const uint8_t *tab8, const uint8_t *sqt, float4 *thick) {
+                            const uint8_t *tab8, float4 *thick) {
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     float *bins = reinterpret_cast<float *>(lds + L.bins);
     uint32_t *flgm = reinterpret_cast<uint32_t *>(lds + L.flgm);
@@ -970,10 +1001,10 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
                         const int r = lane >> 3, k = lane & 7;
                         const uint32_t rg = r < npop ? Fc[c0 + r] : 0u;
                         const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
-                        bool open = false, enq = false, face1 = false;
+                        bool open = false, enq = false, far1 = false;
                         uint32_t push = 0, pk = 0;
                         if (node >= 0)
-                            visit_node<false>(A, node, T, G, n_b, n_h, n_open, open, push, enq, pk, face1);
+                            visit_node<false>(A, node, T, G, n_b, n_h, n_open, open, push, enq, pk, far1);
                         const uint64_t bal = __ballot(open);
                         const int npush = __builtin_popcountll(bal);
                         if (npush) {
@@ -984,9 +1015,9 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
                             if (open && pos < fcap) Fn[pos] = push;
                             if (base + npush > fcap && lane == 0) atomicOr(A.err, 4);
                         }
-                        const uint64_t fb = __ballot(enq && face1), gb = __ballot(enq && !face1);
+                        const uint64_t fb = __ballot(enq && far1), gb = __ballot(enq && !far1);
                         if (enq) {
-                            const int qp = face1 ? qf + __builtin_popcountll(fb & below)
+                            const int qp = far1 ? qf + __builtin_popcountll(fb & below)
                                                  : kQueue - 1 - qs - __builtin_popcountll(gb & below);
                             qnode[qp] = node;
                             qpk[qp] = pk;
@@ -996,14 +1027,14 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
                         wave_sync();
                         if (qf >= 64) {
                             const int e = qf - 64 + lane;
-                            map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flgm, thick,
+                            map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick,
                                                         flgt);
                             qf -= 64;
                             wave_sync();
                         }
                         if (qs >= 64) {
                             const int e = kQueue - qs + lane;
-                            map_queue<true, false, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flgm, thick,
+                            map_queue<true, false, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick,
                                                          flgt);
                             qs -= 64;
                             wave_sync();
@@ -1020,14 +1051,14 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
             if (qf > 0) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = lane < nq ? qf - nq + lane : -1;
-                map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flgm, thick, flgt);
+                map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt);
                 qf -= nq;
                 wave_sync();
             }
             if (qs > 0) {
                 const int nq = qs >= 64 ? 64 : qs;
                 const int e = lane < nq ? kQueue - qs + lane : -1;
-                map_queue<true, false, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, sqt, bins, flgm, thick, flgt);
+                map_queue<true, false, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt);
                 qs -= nq;
                 wave_sync();
             }
@@ -1123,9 +1154,9 @@ __global__ __launch_bounds__(1024) void k_trace_coop(TraceArgs A) {
     const int ncell = 6 << (2 * A.log2m);
     uint8_t *t = reinterpret_cast<uint8_t *>(smem);
     for (int k = threadIdx.x; k < ncell; k += blockDim.x) t[k] = (uint8_t)A.table[k];
-    for (int k = threadIdx.x; k < ncell / 2; k += blockDim.x) t[ncell + k] = A.square[k];
+
     __syncthreads();
-    const uint8_t *tab8 = t, *sqt = t + ncell;
+    const uint8_t *tab8 = t;
     char *lds = smem + A.lds_table;
     const int fcap = A.fcap;
     const CoopLayout L = coop_layout(A.npix, A.bp, fcap, blockDim.x >> 6);
@@ -1143,7 +1174,7 @@ __global__ __launch_bounds__(1024) void k_trace_coop(TraceArgs A) {
             const int ti = *target + lo;
             __syncthreads();
             if (ti >= hi) break;
-            coop_target(A, ti, lds, L, fcap, tab8, sqt, thick);
+            coop_target(A, ti, lds, L, fcap, tab8, thick);
         }
     }
 }
@@ -1168,7 +1199,6 @@ struct BatchArgs {
     int lds_table;
     int n_tab;
     const int16_t *tab[kMaxTabs];
-    const uint8_t *sq[kMaxTabs];
     int tab_off[kMaxTabs];
     int tab_ncell[kMaxTabs];
     float4 *thick;
@@ -1183,7 +1213,6 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace_batch(BatchArg
             uint8_t *t = reinterpret_cast<uint8_t *>(smem) + B.tab_off[s];
             const int nc = B.tab_ncell[s];
             for (int k = threadIdx.x; k < nc; k += blockDim.x) t[k] = (uint8_t)B.tab[s][k];
-            for (int k = threadIdx.x; k < nc / 2; k += blockDim.x) t[nc + k] = B.sq[s][k];
         }
         __syncthreads();
     }
@@ -1211,8 +1240,7 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace_batch(BatchArg
                 const int k = __builtin_amdgcn_readfirstlane(a);
                 const TraceArgs &A = B.inst[k];
                 const uint8_t *tab8 = reinterpret_cast<const uint8_t *>(smem) + B.tab_off[A.tab_slot];
-                const uint8_t *sqt = LDS_TABLE ? tab8 + B.tab_ncell[A.tab_slot] : A.square;
-                trace_target<NSLOT, false, LDS_TABLE>(A, (ti - B.start[k]) * B.stride, lds, tab8, sqt, thick);
+                trace_target<NSLOT, false, LDS_TABLE>(A, (ti - B.start[k]) * B.stride, lds, tab8, thick);
             }
         }
     }
@@ -1261,7 +1289,7 @@ struct Inst {
 
 constexpr int kLdsCu = 160 * 1024;
 
-int table_bytes(int M) { return (6 * M * M + 3 * M * M + 15) & ~15; }
+int table_bytes(int M) { return (6 * M * M + 15) & ~15; }
 int max_waves_for(int npix) { return npix > 192 ? 4 : 16; } // the kernel's launch bound
 int nslot_for(int npix) { return npix <= 64 ? 1 : (npix <= 192 ? 3 : 12); }
 
@@ -1295,7 +1323,8 @@ int setup_instance(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, floa
     A = TraceArgs{};
     A.nodes = t->packed; A.q = t->q; A.pcol = t->pcol;
     A.targets = t->targets; A.leaf_cell = t->leaf_cell; A.cell_tau = t->cell_tau; A.cell_src = t->cell_src;
-    A.table = I.rt->table; A.square = I.rt->square; A.dirs = I.rt->dirs;
+    A.table = I.rt->table; A.alpha = I.rt->alpha; A.dirs = I.rt->dirs;
+    A.per_node = p->per_node_kernel ? 1 : 0;
     A.work = ctx->d_ctl; A.err = ctx->d_ctl + 16;
     A.J = J; A.F = F; A.u_rad = u_rad; A.counters = counters;
     A.n_cells = t->n_cells; A.n_targets = (int)t->n_cells; A.root_edge = (int)t->root_edge;
@@ -1650,7 +1679,6 @@ int batch_build(tr_ctx *ctx, int n, const tr_tree *const *trees, const tr_trace_
             slot = (int)b->tabs.size();
             b->tabs.push_back(key);
             b->B.tab[slot] = I.rt->table;
-            b->B.sq[slot] = I.rt->square;
             b->B.tab_ncell[slot] = 6 * I.M * I.M;
         }
         I.A.tab_slot = slot;

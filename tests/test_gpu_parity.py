@@ -87,6 +87,14 @@ def test_ray_tables_equal_oracle(lib, ctx, ns):
     assert np.abs(dirs - oracle.ray_dirs(ns)).max() < 1e-6
 
 
+@pytest.mark.parametrize("ns", [1, 2, 4, 8])
+def test_alpha_table_equal_oracle(lib, ctx, ns):
+    """The tabulated angular kernel of distant nodes, built by the library from its pixel
+    table in exact integers: every pixel, count and overflow flag equal to the oracle's."""
+    say("alpha table n_side", ns)
+    assert np.array_equal(lib.alpha_table(ctx, ns), oracle.alpha_table(ns))
+
+
 @pytest.mark.parametrize("case", list(TREE_CASES))
 def test_tree_bit_exact(lib, ctx, case):
     from paper_2204_09072_amd.run import tree_of, upload
@@ -163,6 +171,19 @@ def test_trace_parity_all_targets(lib, ctx, case, bpp, kernel):
     Jo, Fo = ot.trace(oracle.params(w.n_side, theta=w.theta))
     _check_trace(J.cpu().numpy(), F.cpu().numpy().T, Jo, Fo)
     assert np.allclose(U.cpu().numpy(), 4 * np.pi * J.cpu().numpy() / w.units[1], rtol=1e-6)
+
+
+@pytest.mark.parametrize("case,kernel", [("turb32", 1), ("amr_small", 2), ("padded40", 1)])
+def test_trace_parity_per_node_kernel(lib, ctx, case, kernel):
+    """The per-node 8-point kernel for every node (no table) against the oracle run the
+    same way."""
+    from paper_2204_09072_amd.run import trace
+    w = TREE_CASES[case]()
+    say("trace per-node kernel", case, "kernel", kernel)
+    tree, J, F, U = trace(ctx, w, kernel=kernel, per_node_kernel=True)
+    ctx.sync()
+    Jo, Fo = oracle.Tree(w).trace(oracle.params(w.n_side, theta=w.theta, alpha_table=False))
+    _check_trace(J.cpu().numpy(), F.cpu().numpy().T, Jo, Fo)
 
 
 def test_trace_parity_merge_off_and_background(lib, ctx):
