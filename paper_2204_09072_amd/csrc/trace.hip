@@ -30,6 +30,8 @@ constexpr float kPiF = 3.14159265358979f;
 // 0, the near-node one down from kQueue - 1; each holds < 64 entries before a walk step
 // adds at most 64
 constexpr int kQueue = 192;
+// far-node entries also carry their table key, radial kernel and V_thick (positions < 128)
+constexpr int kFarQ = 128;
 constexpr int kFields = 6;  // L_thin, A_thin, L_thick*V, A_thick, V_thick, Q
 constexpr int kThin = 2;    // fields held in LDS: L_thin, A_thin
 constexpr int kMaxBp = 16;  // segments per pass: merge flags in bits 0-15 of a ray's flag
@@ -82,7 +84,7 @@ struct TraceArgs {
 };
 
 struct LdsLayout {
-    int bins, flg, stk, qnode, qpk, total;
+    int bins, flg, stk, qnode, qpk, qmeta, total;
 };
 
 __host__ __device__ inline LdsLayout lds_layout(int npix, int bp, int kstack, bool count) {
@@ -98,6 +100,8 @@ __host__ __device__ inline LdsLayout lds_layout(int npix, int bp, int kstack, bo
     o += count ? 0 : kQueue * 4;
     L.qpk = o;
     o += count ? 0 : kQueue * 4;
+    L.qmeta = o;
+    o += count ? 0 : kFarQ * 12;
     L.total = (o + 15) & ~15;
     return L;
 }
@@ -263,6 +267,25 @@ __device__ __forceinline__ bool far_node(int dx, int dy, int dz, int s) {
     return r2 >= 64 * sf * sf;
 }
 
+// table index of a far node: direction cell of the offset in the ray set's frame and
+// distance class c = floor(log2(r^2 / s^2)) from the leading bits, corrected once
+__device__ __forceinline__ int alpha_key(int dx, int dy, int dz, int s, int orient, int log2m) {
+    const int64_t r2 = (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz;
+    const int64_t sf = (int64_t)TR_FX * s, s2 = sf * sf;
+    int c = (63 - __clzll(r2)) - (63 - __clzll(s2));
+    if ((s2 << c) > r2) --c;
+    c = c > kAlphaMax ? kAlphaMax : c;
+    orient_offset(orient, dx, dy, dz);
+    return cube_cell(dx, dy, dz, log2m) * kAlphaClasses + (c - kAlphaFar);
+}
+
+// radial kernel beta = R_i^2 / r^2 of segment i (offsets in 1/256 lattice units)
+__device__ __forceinline__ float beta_of(int dx, int dy, int dz, int i) {
+    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+    const float R2 = (float)(TR_FX * i * i);
+    return (R2 * R2) * rcp(fx * fx + fy * fy + fz * fz);
+}
+
 // Queue record of an accepted node: pk = content segment (i - a + 1, 0 = none) | first
 // merge flag << 6 | end of merge flags << 12 (both relative to the pass) | leaf << 18 |
 // depth << 19.
@@ -273,11 +296,14 @@ __device__ __forceinline__ bool far_node(int dx, int dy, int dz, int s) {
 // sub-points, each binned to a direction cell and its pixel, sorted to find the distinct
 // pixels.  SPLIT: merge flags in flg and thick-content flags in flgt, one bit per segment
 // of the pass each (passes of up to 31 segments); otherwise both in flg (thick bits from
-// bit 16).
-template <bool LDS_TABLE, bool FAR, bool SPLIT = false>
+// bit 16).  META: far entries bring their table key, beta and V_thick from the walk, so
+// that the node's sums and its table entry are fetched side by side.
+template <bool LDS_TABLE, bool FAR, bool SPLIT = false, bool META = false>
 __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *qnode, const uint32_t *qpk,
                                           int pass_a, int4 c256, int orient, const uint8_t *tab8, float *bins,
-                                          uint32_t *flg, float4 *thick, uint32_t *flgt = nullptr) {
+                                          uint32_t *flg, float4 *thick, uint32_t *flgt = nullptr,
+                                          const int *qkey = nullptr, const float *qbeta = nullptr,
+                                          const float *qvk = nullptr) {
     uint32_t starts = 0;
     int pix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     float Lt = 0, At = 0, LVk = 0, Ak = 0, Vk = 0, beta = 0;
@@ -294,7 +320,21 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
         const uint32_t k0 = (pk >> 6) & 63u, k1 = (pk >> 12) & 63u;
         if (k1 > k0) fbits = (k1 >= 32u ? 0xffffffffu : ((1u << k1) - 1u)) & ~((1u << k0) - 1u);
         const float4 qv = A.q[node];
-        const int4 p = A.pcol[node];
+        int4 en = make_int4(0, 0, 0, 1);
+        float vkh;
+        int dx = 0, dy = 0, dz = 0;
+        if (FAR && META) {
+            en = A.alpha[qkey[e]];
+            beta = qbeta[e];
+            vkh = qvk[e];
+        } else {
+            const int4 p = A.pcol[node];
+            vkh = __int_as_float(p.w);
+            dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
+            if (seg >= 0) beta = beta_of(dx, dy, dz, seg + pass_a);
+            if (FAR) en = A.alpha[alpha_key(dx, dy, dz, s, orient, A.log2m)];
+            orient_offset(orient, dx, dy, dz); // the angular kernel works in the ray set's frame
+        }
         if (leaf) {
             const bool thick = signbit(qv.x);
             const float V = (float)s * (float)s * (float)s;
@@ -305,34 +345,22 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             Vk = thick ? V : 0.0f;
         } else {
             Lt = qv.x; LVk = qv.y; At = qv.z; Ak = qv.w;
-            Vk = __int_as_float(p.w);
+            Vk = vkh;
         }
-        int dx = p.x - c256.x, dy = p.y - c256.y, dz = p.z - c256.z;
-        if (seg >= 0) {
-            // radial kernel beta = R_i^2 / r^2
-            const int i = seg + pass_a;
-            const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-            const float R2 = (float)(TR_FX * i * i);
-            beta = (R2 * R2) * rcp(fx * fx + fy * fy + fz * fz);
-        }
-        orient_offset(orient, dx, dy, dz); // the angular kernel works in the ray set's frame
         auto lookup = [&](int cell) { return LDS_TABLE ? (int)tab8[cell] : (int)A.table[cell]; };
-        if (FAR) {
-            // distance class: c = floor(log2(r^2 / s^2)) from the leading bits, corrected once
-            const int64_t r2 = (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz;
-            const int64_t sf = (int64_t)TR_FX * s, s2 = sf * sf;
-            int c = (63 - __clzll(r2)) - (63 - __clzll(s2));
-            if ((s2 << c) > r2) --c;
-            c = c > kAlphaMax ? kAlphaMax : c;
-            const int4 en = A.alpha[cube_cell(dx, dy, dz, A.log2m) * kAlphaClasses + (c - kAlphaFar)];
-            if (en.w == 0) {
-                tab = true;
-                pix[0] = en.x & 0xffff;
-                pix[1] = (int)((uint32_t)en.x >> 16);
-                pix[2] = en.y & 0xffff;
-                pix[3] = (int)((uint32_t)en.y >> 16);
-                counts = (uint32_t)en.z;
-            }
+        if (FAR && en.w == 0) {
+            tab = true;
+            pix[0] = en.x & 0xffff;
+            pix[1] = (int)((uint32_t)en.x >> 16);
+            pix[2] = en.y & 0xffff;
+            pix[3] = (int)((uint32_t)en.y >> 16);
+            counts = (uint32_t)en.z;
+        }
+        if (FAR && META && !tab) {
+            // a key that reaches more than 4 pixels: the per-node kernel needs the offset
+            const int4 p = A.pcol[node];
+            dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
+            orient_offset(orient, dx, dy, dz);
         }
         if (!tab) {
             const int h = (TR_FX / 4) * s;
@@ -351,58 +379,39 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             starts = 1u;
 #pragma unroll
             for (int k = 1; k < 8; ++k) starts |= (pix[k] != pix[k - 1] ? 1u : 0u) << k;
-        } else {
-            // one "run" per tabulated pixel with a non-zero count
-#pragma unroll
-            for (int k = 0; k < 4; ++k) starts |= (((counts >> (8 * k)) & 255u) != 0u ? 1u : 0u) << k;
         }
     }
-    // one update per distinct pixel; the loop runs as often as the busiest lane needs.  Thin
+    // One update per (node, pixel); each loop runs as often as the busiest lane needs.  Thin
     // contributions are first summed over runs of neighbouring lanes that hit the same
     // (pixel, segment) -- siblings of one parent usually do -- so that one LDS atomic per
     // run, not per lane, reaches the bins.
     const int lane = lane_id(), rl = lane & 15;
-    while (__ballot(starts != 0u)) {
-        int key = -1;
-        float v0 = 0.0f, v1 = 0.0f;
-        if (starts) {
-            const int k = __builtin_ctz(starts);
-            starts &= starts - 1u;
-            int px = pix[0];
-#pragma unroll
-            for (int j = 1; j < 8; ++j) px = k == j ? pix[j] : px;
-            float al;
-            if (FAR && tab) {
-                al = (1.0f / 64.0f) * (float)((counts >> (8 * k)) & 255u);
-            } else {
-                const int kn = starts ? __builtin_ctz(starts) : 8;
-                al = 0.125f * (float)(kn - k);
-            }
-            uint32_t fl = fbits, ft = 0u;
-            if (seg >= 0) {
-                const float ab = al * beta;
-                key = px * A.bp + seg;
-                v0 = ab * Lt;
-                v1 = ab * At;
-                if (Vk > 0.0f) {
-                    float *tk = reinterpret_cast<float *>(thick + px * A.bp + seg);
-                    atomicAdd(tk + 0, al * LVk);
-                    atomicAdd(tk + 1, al * Ak);
-                    atomicAdd(tk + 2, al * Vk);
-                    atomicAdd(tk + 3, ab * Vk);
-                    ft = 1u << seg;
-                }
-            }
-            if (SPLIT) {
-                if (fl) atomicOr(flg + px, fl);
-                if (ft) atomicOr(flgt + px, ft);
-            } else {
-                fl |= ft << 16;
-                if (fl) atomicOr(flg + px, fl);
+    auto update = [&](int px, float al, float ab, int &key, float &v0, float &v1) {
+        uint32_t fl = fbits, ft = 0u;
+        if (seg >= 0) {
+            key = px * A.bp + seg;
+            v0 = ab * Lt;
+            v1 = ab * At;
+            if (Vk > 0.0f) {
+                float *tk = reinterpret_cast<float *>(thick + px * A.bp + seg);
+                atomicAdd(tk + 0, al * LVk);
+                atomicAdd(tk + 1, al * Ak);
+                atomicAdd(tk + 2, al * Vk);
+                atomicAdd(tk + 3, ab * Vk);
+                ft = 1u << seg;
             }
         }
-        // runs of equal keys within rows of 16 lanes (wave-uniform control flow from here):
-        // run id = number of run heads up to this lane, then a segmented inclusive sum
+        if (SPLIT) {
+            if (fl) atomicOr(flg + px, fl);
+            if (ft) atomicOr(flgt + px, ft);
+        } else {
+            fl |= ft << 16;
+            if (fl) atomicOr(flg + px, fl);
+        }
+    };
+    auto flush = [&](int key, float v0, float v1) {
+        // runs of equal keys within rows of 16 lanes (wave-uniform control flow): run id =
+        // number of run heads up to this lane, then a segmented inclusive sum
         const int prev = dpp_shr<1>(key, -2);
         const bool head = rl == 0 || prev != key;
         const uint64_t hb = __ballot(head);
@@ -417,6 +426,38 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             if (v0 != 0.0f) atomicAdd(bb + 0, v0);
             if (v1 != 0.0f) atomicAdd(bb + 1, v1);
         }
+    };
+    if (FAR) {
+        // tabulated entries: slot t holds the t-th pixel, count 0 = unused (slots are filled
+        // from 0), so the slot index is the same on every lane
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t ct = tab ? (counts >> (8 * t)) & 255u : 0u;
+            if (!__ballot(ct != 0u)) break;
+            int key = -1;
+            float v0 = 0.0f, v1 = 0.0f;
+            if (ct) {
+                const float al = (1.0f / 64.0f) * (float)ct;
+                update(pix[t], al, al * beta, key, v0, v1);
+            }
+            flush(key, v0, v1);
+        }
+    }
+    // per-node kernel: runs of equal pixels among the 8 sorted sub-point pixels
+    while (__ballot(starts != 0u)) {
+        int key = -1;
+        float v0 = 0.0f, v1 = 0.0f;
+        if (starts) {
+            const int k = __builtin_ctz(starts);
+            starts &= starts - 1u;
+            int px = pix[0];
+#pragma unroll
+            for (int j = 1; j < 8; ++j) px = k == j ? pix[j] : px;
+            const int kn = starts ? __builtin_ctz(starts) : 8;
+            const float al = 0.125f * (float)(kn - k);
+            update(px, al, al * beta, key, v0, v1);
+        }
+        flush(key, v0, v1);
     }
 }
 
@@ -582,6 +623,9 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
     uint32_t *stk = reinterpret_cast<uint32_t *>(lds + LL.stk);
     int *qnode = reinterpret_cast<int *>(lds + LL.qnode);
     uint32_t *qpk = reinterpret_cast<uint32_t *>(lds + LL.qpk);
+    int *qkey = reinterpret_cast<int *>(lds + LL.qmeta);
+    float *qbeta = reinterpret_cast<float *>(qkey + kFarQ);
+    float *qvk = qbeta + kFarQ;
     const int lane = lane_id();
     const int tid = A.targets[ti];
     const int4 tr = A.nodes[tid];
@@ -624,6 +668,8 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                 const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
                 bool open = false, enq = false, far1 = false;
                 uint32_t push = 0, pk = 0;
+                int fkey = 0;
+                float fbeta = 0.0f, fvk = 0.0f;
                 if (node >= 0) {
                     const int4 nd = A.nodes[node];
                     const int depth = (nd.x >> 16) & 15;
@@ -692,12 +738,13 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                             maybe = rmax2 >= a4 && (last || rmin2 < b4);
                         }
                         if (maybe) {
-                            int dx, dy, dz;
+                            int dx, dy, dz, pw = 0;
                             if (leaf) {
                                 dx = vx * TR_FX; dy = vy * TR_FX; dz = vz * TR_FX;
                             } else {
                                 const int4 p = A.pcol[node];
                                 dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
+                                pw = p.w;
                             }
                             const int i = bin_below(dx, dy, dz, 0, A.n_bins);
                             if (i > 0) {
@@ -718,6 +765,11 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                                          ((uint32_t)k1 << 12) | ((leaf ? 1u : 0u) << 18) |
                                          ((uint32_t)depth << 19);
                                     far1 = !A.per_node && far_node(dx, dy, dz, s);
+                                    if (far1) {
+                                        fkey = alpha_key(dx, dy, dz, s, orient, A.log2m);
+                                        fbeta = content ? beta_of(dx, dy, dz, i) : 0.0f;
+                                        fvk = __int_as_float(pw);
+                                    }
                                 }
                             }
                         }
@@ -741,6 +793,11 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                                              : kQueue - 1 - qs - __builtin_popcountll(gb & below);
                         qnode[qp] = node;
                         qpk[qp] = pk;
+                        if (far1) {
+                            qkey[qp] = fkey;
+                            qbeta[qp] = fbeta;
+                            qvk[qp] = fvk;
+                        }
                     }
                     qf += __builtin_popcountll(fb);
                     qs += __builtin_popcountll(gb);
@@ -752,7 +809,8 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
             if (qf >= 64 || (sp == 0 && qf > 0)) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = lane < nq ? qf - nq + lane : -1;
-                map_queue<LDS_TABLE, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick);
+                map_queue<LDS_TABLE, true, false, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick,
+                                                        nullptr, qkey, qbeta, qvk);
                 qf -= nq;
                 wave_sync();
             }
@@ -1292,6 +1350,10 @@ constexpr int kLdsCu = 160 * 1024;
 int table_bytes(int M) { return (6 * M * M + 15) & ~15; }
 int max_waves_for(int npix) { return npix > 192 ? 4 : 16; } // the kernel's launch bound
 int nslot_for(int npix) { return npix <= 64 ? 1 : (npix <= 192 ? 3 : 12); }
+// the one-wave kernels keep the pixel table in LDS for up to 64 rays (N_side <= 2, at most
+// 6 KB); beyond that only near nodes read it, from global memory, and the LDS holds more
+// segments per pass instead
+bool table_in_lds(int npix) { return npix <= 64; }
 
 int setup_instance(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float *J, float *F, float *u_rad,
                    int32_t *counters, bool count, Inst &I) {
@@ -1426,7 +1488,7 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     if (rc) return rc;
     if (p->kernel < 0 || p->kernel > 2) return tr_fail(ctx, TR_EINVAL, "kernel must be 0, 1 or 2");
     const int npix = I.npix;
-    const bool tab_lds = !count && npix <= 256;
+    const bool tab_lds = !count && table_in_lds(npix);
     const int lds_table = tab_lds ? table_bytes(I.M) : 0;
     const int max_waves = max_waves_for(npix);
     // automatic choice: the one-block-per-target kernel when the one-wave kernel would need
@@ -1436,7 +1498,7 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     const bool many_passes =
         tr_div_up(I.A.n_bins, choose_bp(I, p->bins_per_pass, lds_table, max_waves, count)) >= 12;
     if (!count && (p->kernel == 2 || (p->kernel == 0 && many_passes))) {
-        rc = launch_coop(ctx, I, p, lds_table);
+        rc = launch_coop(ctx, I, p, npix <= 256 ? table_bytes(I.M) : 0);
         if (rc != TR_ENOTSUP) return rc;
         if (p->kernel == 2) return tr_fail(ctx, TR_EINVAL, "the one-block-per-target kernel does not fit this case");
         ctx->err.clear();
@@ -1470,7 +1532,7 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     } else if (nslot_for(npix) == 1) {
         LAUNCH(1, false, true);
     } else if (nslot_for(npix) == 3) {
-        LAUNCH(3, false, true);
+        LAUNCH(3, false, false);
     } else {
         LAUNCH(12, false, false);
     }
@@ -1589,7 +1651,7 @@ int batch_enqueue(tr_batch *b, hipStream_t st, bool sample) {
     if (b->nslot == 1) {
         LAUNCHB(1, true);
     } else if (b->nslot == 3) {
-        LAUNCHB(3, true);
+        LAUNCHB(3, false);
     } else {
         LAUNCHB(12, false);
     }
@@ -1684,7 +1746,7 @@ int batch_build(tr_ctx *ctx, int n, const tr_tree *const *trees, const tr_trace_
         I.A.tab_slot = slot;
     }
     b->nslot = nslot_for(max_npix);
-    b->tab_lds = max_npix <= 256;
+    b->tab_lds = table_in_lds(max_npix);
     b->B.n_tab = (int)b->tabs.size();
     int off = 0;
     for (int s = 0; s < b->B.n_tab; ++s) {
