@@ -116,12 +116,14 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // largest i in [0, nb] with R_i + off <= r (lattice units / 256, R_i = 256 i^2), i.e.
-// (256 i^2 + off)^2 <= r2 or 256 i^2 + off <= 0.  Float estimate, exact fallback near edges.
+// (256 i^2 + off)^2 <= r2 or 256 i^2 + off <= 0.  Float estimate (hardware square root,
+// 1 ulp; the sum of squares adds a few more, far inside the 4e-6 r margin), exact
+// integer fallback near edges.
 __device__ __forceinline__ int bin_below(int dx, int dy, int dz, int off, int nb) {
     const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-    const float r = sqrtf(fx * fx + fy * fy + fz * fz);
+    const float r = __builtin_amdgcn_sqrtf(fx * fx + fy * fy + fz * fz);
     const float x = r - (float)off;
-    int i = x > 0.0f ? (int)sqrtf(x * (1.0f / TR_FX)) : 0;
+    int i = x > 0.0f ? (int)__builtin_amdgcn_sqrtf(x * (1.0f / TR_FX)) : 0;
     i = i > nb ? nb : i;
     const float e0 = (float)(TR_FX * i * i), e1 = (float)(TR_FX * (i + 1) * (i + 1));
     const float tol = 4e-6f * (r + (float)(off < 0 ? -off : off) + 1.0f);
@@ -260,23 +262,66 @@ constexpr int kAlphaFar = 6;
 constexpr int kAlphaMax = 20;
 constexpr int kAlphaClasses = kAlphaMax - kAlphaFar + 1;
 
-// a node is served by the table when r^2 >= 64 s^2 (all in 1/256 lattice units)
-__device__ __forceinline__ bool far_node(int dx, int dy, int dz, int s) {
+// distance class c = floor(log2(r^2 / s^2)) of an offset (1/256 lattice units, r^2 > 0)
+// from a node of edge s = 2^log2s: node edges are powers of two, so s^2 = 2^(16 + 2 log2s)
+// and c is exact from the leading bit of r^2.  The node is served by the table when c >= 6,
+// i.e. r^2 >= 64 s^2.
+__device__ __forceinline__ int dist_class(int dx, int dy, int dz, int log2s) {
     const int64_t r2 = (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz;
-    const int64_t sf = (int64_t)TR_FX * s;
-    return r2 >= 64 * sf * sf;
+    return (63 - __clzll(r2)) - 2 * (8 + log2s);
 }
 
-// table index of a far node: direction cell of the offset in the ray set's frame and
-// distance class c = floor(log2(r^2 / s^2)) from the leading bits, corrected once
-__device__ __forceinline__ int alpha_key(int dx, int dy, int dz, int s, int orient, int log2m) {
-    const int64_t r2 = (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz;
-    const int64_t sf = (int64_t)TR_FX * s, s2 = sf * sf;
-    int c = (63 - __clzll(r2)) - (63 - __clzll(s2));
-    if ((s2 << c) > r2) --c;
+// table index of a far node (class c >= 6): direction cell of the offset in the ray set's
+// frame and the class, larger classes counting as the last
+__device__ __forceinline__ int alpha_key(int dx, int dy, int dz, int c, int orient, int log2m) {
     c = c > kAlphaMax ? kAlphaMax : c;
     orient_offset(orient, dx, dy, dz);
     return cube_cell(dx, dy, dz, log2m) * kAlphaClasses + (c - kAlphaFar);
+}
+
+// Segment of an accepted node in the pass [a, b) (Sec. 4.2): i = the largest radial point
+// with R_i <= r (R_i = i^2 lattice units, offsets in 1/256 units), content when a <= i < b
+// (or i >= a in the last pass).  A node with thick material and merging (ext = s/2 > 0)
+// also flags the segments its extent r -+ s/2 spans, k0 .. k1 relative to a.  Without
+// thick material r^2 is compared with (256 i^2)^2 exactly in 64 bits, for the points of
+// the pass only when it holds a few.
+struct SegHit {
+    int i, k0, k1;
+    bool content;
+};
+__device__ __forceinline__ SegHit seg_hit(int dx, int dy, int dz, int s, int ext, int a, int b, bool last, int nb) {
+    SegHit h{0, 0, 0, false};
+    if (ext) {
+        const int i = bin_below(dx, dy, dz, 0, nb);
+        if (i > 0) {
+            h.i = i;
+            h.content = i >= a && i < b;
+            const int half = TR_FX / 2 * s;
+            int lo = bin_below(dx, dy, dz, half, nb);
+            lo = lo < 1 ? 1 : lo;
+            const int hi = bin_below(dx, dy, dz, -half, nb);
+            int k0 = lo > a ? lo : a, k1 = hi < b ? hi : b;
+            if (k1 > k0) {
+                h.k0 = k0 - a;
+                h.k1 = k1 - a;
+            }
+        }
+    } else {
+        const int64_t r2 = (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz;
+        auto t = [](int k) {
+            const int64_t q = (int64_t)TR_FX * k * k;
+            return q * q;
+        };
+        h.content = r2 >= t(a) && (last || r2 < t(b));
+        if (b - a <= 4) {
+            int i = a;
+            for (int k = a + 1; k < b; ++k) i += r2 >= t(k) ? 1 : 0;
+            h.i = i;
+        } else {
+            h.i = bin_below(dx, dy, dz, 0, nb); // wide passes: float estimate, exact near edges
+        }
+    }
+    return h;
 }
 
 // radial kernel beta = R_i^2 / r^2 of segment i (offsets in 1/256 lattice units)
@@ -332,7 +377,10 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             vkh = __int_as_float(p.w);
             dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
             if (seg >= 0) beta = beta_of(dx, dy, dz, seg + pass_a);
-            if (FAR) en = A.alpha[alpha_key(dx, dy, dz, s, orient, A.log2m)];
+            if (FAR) {
+                const int log2s = (31 - __clz(A.root_edge)) - (int)((pk >> 19) & 15u);
+                en = A.alpha[alpha_key(dx, dy, dz, dist_class(dx, dy, dz, log2s), orient, A.log2m)];
+            }
             orient_offset(orient, dx, dy, dz); // the angular kernel works in the ray set's frame
         }
         if (leaf) {
@@ -429,7 +477,8 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
     };
     if (FAR) {
         // tabulated entries: slot t holds the t-th pixel, count 0 = unused (slots are filled
-        // from 0), so the slot index is the same on every lane
+        // from 0), so the slot index is the same on every lane.  Every lane has a slot 0;
+        // later slots are sparse and go to the bins directly.
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const uint32_t ct = tab ? (counts >> (8 * t)) & 255u : 0u;
@@ -440,7 +489,13 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
                 const float al = (1.0f / 64.0f) * (float)ct;
                 update(pix[t], al, al * beta, key, v0, v1);
             }
-            flush(key, v0, v1);
+            if (t == 0) {
+                flush(key, v0, v1);
+            } else if (key >= 0) {
+                float *bb = bins + key * kThin;
+                if (v0 != 0.0f) atomicAdd(bb + 0, v0);
+                if (v1 != 0.0f) atomicAdd(bb + 1, v1);
+            }
         }
     }
     // per-node kernel: runs of equal pixels among the 8 sorted sub-point pixels
@@ -514,7 +569,8 @@ struct PassGeo {
 template <bool COUNT>
 __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const Target &T, const PassGeo &G,
                                            int &n_b, int &n_h, int &n_open, bool &open, uint32_t &push,
-                                           bool &enq, uint32_t &pk, bool &far1) {
+                                           bool &enq, uint32_t &pk, bool &far1, int &fkey, float &fbeta,
+                                           float &fvk) {
     const int4 nd = A.nodes[node];
     const int depth = (nd.x >> 16) & 15;
     const bool leaf = (nd.x >> 20) & 1;
@@ -582,41 +638,50 @@ __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const T
             maybe = rmax2 >= G.a4 && (G.last || rmin2 < G.b4);
         }
         if (maybe) {
-            int dx, dy, dz;
+            int dx, dy, dz, pw = 0;
             if (leaf) {
                 dx = vx * TR_FX; dy = vy * TR_FX; dz = vz * TR_FX;
             } else {
                 const int4 p = A.pcol[node];
                 dx = p.x - T.c256.x; dy = p.y - T.c256.y; dz = p.z - T.c256.z;
+                pw = p.w;
             }
-            const int i = bin_below(dx, dy, dz, 0, A.n_bins);
-            if (i > 0) {
-                const bool content = i >= G.a && i < G.b;
-                int k0 = 0, k1 = 0;
-                if (ext) {
-                    const int half = TR_FX / 2 * s;
-                    int lo = bin_below(dx, dy, dz, half, A.n_bins);
-                    lo = lo < 1 ? 1 : lo;
-                    const int hi = bin_below(dx, dy, dz, -half, A.n_bins);
-                    k0 = lo > G.a ? lo : G.a;
-                    k1 = hi < G.b ? hi : G.b;
-                    if (k1 <= k0) { k0 = 0; k1 = 0; } else { k0 -= G.a; k1 -= G.a; }
-                }
-                if (content || k1 > k0) {
-                    enq = true;
-                    pk = (content ? (uint32_t)(i - G.a + 1) : 0u) | ((uint32_t)k0 << 6) |
-                         ((uint32_t)k1 << 12) | ((leaf ? 1u : 0u) << 18) |
-                         ((uint32_t)depth << 19);
-                    far1 = !A.per_node && far_node(dx, dy, dz, s);
+            const SegHit h = seg_hit(dx, dy, dz, s, ext, G.a, G.b, G.last, A.n_bins);
+            if (h.content || h.k1 > h.k0) {
+                enq = true;
+                pk = (h.content ? (uint32_t)(h.i - G.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
+                     ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) | ((uint32_t)depth << 19);
+                const int c = dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth);
+                far1 = !A.per_node && c >= kAlphaFar;
+                if (far1) {
+                    fkey = alpha_key(dx, dy, dz, c, T.orient, A.log2m);
+                    fbeta = h.content ? beta_of(dx, dy, dz, h.i) : 0.0f;
+                    fvk = __int_as_float(pw);
                 }
             }
         }
     }
 }
 
-template <int NSLOT, bool COUNT, bool LDS_TABLE>
-__device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_t *tab8,
+// The arguments of a single-instance launch (the kernel's only argument) are read from the
+// kernel-argument segment where they are used (scalar loads), not held in scalar registers
+// across the persistent loop: there are more of them than registers, and the spilled
+// copies cost vector instructions to restore.  The empty asm hides the segment pointer's
+// value from the compiler so that the loads stay where they are.  Batched launches take
+// the instance's descriptor as given.
+typedef __attribute__((address_space(4))) const TraceArgs *KernArgs;
+template <bool KARG>
+__device__ __forceinline__ const TraceArgs &args_at(const TraceArgs &given) {
+    if (!KARG) return given;
+    KernArgs p = (KernArgs)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(const TraceArgs *)p;
+}
+
+template <int NSLOT, bool COUNT, bool LDS_TABLE, bool KARG = false>
+__device__ void trace_target(const TraceArgs &A0, int ti, char *lds, const uint8_t *tab8,
                              float4 *thick) {
+    const TraceArgs &A = args_at<KARG>(A0);
     const LdsLayout LL = lds_layout(A.npix, A.bp, A.kstack, COUNT);
     float *bins = reinterpret_cast<float *>(lds + LL.bins);
     uint32_t *flg = reinterpret_cast<uint32_t *>(lds + LL.flg);
@@ -643,6 +708,7 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
     int n_b = 0, n_h = 0, n_open = 0;
     const int n_pass = COUNT ? 1 : A.n_pass;
     for (int ps = 0; ps < n_pass; ++ps) {
+        const TraceArgs &A = args_at<KARG>(A0);
         Pass P;
         P.a = 1 + ps * A.bp;
         P.b = P.a + A.bp;
@@ -659,6 +725,7 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
         int sp = 1, qf = 0, qs = 0; // stack depth, far and near queue lengths
         wave_sync();
         while (sp > 0 || qf > 0 || qs > 0) {
+            const TraceArgs &A = args_at<KARG>(A0);
             if (sp > 0) {
                 const int npop = sp < 8 ? sp : 8;
                 const int r = lane >> 3, k = lane & 7;
@@ -746,30 +813,18 @@ __device__ void trace_target(const TraceArgs &A, int ti, char *lds, const uint8_
                                 dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
                                 pw = p.w;
                             }
-                            const int i = bin_below(dx, dy, dz, 0, A.n_bins);
-                            if (i > 0) {
-                                const bool content = i >= P.a && i < P.b;
-                                int k0 = 0, k1 = 0;
-                                if (ext) {
-                                    const int half = TR_FX / 2 * s;
-                                    int lo = bin_below(dx, dy, dz, half, A.n_bins);
-                                    lo = lo < 1 ? 1 : lo;
-                                    const int hi = bin_below(dx, dy, dz, -half, A.n_bins);
-                                    k0 = lo > P.a ? lo : P.a;
-                                    k1 = hi < P.b ? hi : P.b;
-                                    if (k1 <= k0) { k0 = 0; k1 = 0; } else { k0 -= P.a; k1 -= P.a; }
-                                }
-                                if (content || k1 > k0) {
-                                    enq = true;
-                                    pk = (content ? (uint32_t)(i - P.a + 1) : 0u) | ((uint32_t)k0 << 6) |
-                                         ((uint32_t)k1 << 12) | ((leaf ? 1u : 0u) << 18) |
-                                         ((uint32_t)depth << 19);
-                                    far1 = !A.per_node && far_node(dx, dy, dz, s);
-                                    if (far1) {
-                                        fkey = alpha_key(dx, dy, dz, s, orient, A.log2m);
-                                        fbeta = content ? beta_of(dx, dy, dz, i) : 0.0f;
-                                        fvk = __int_as_float(pw);
-                                    }
+                            const SegHit h = seg_hit(dx, dy, dz, s, ext, P.a, P.b, last, A.n_bins);
+                            if (h.content || h.k1 > h.k0) {
+                                enq = true;
+                                pk = (h.content ? (uint32_t)(h.i - P.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
+                                     ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) |
+                                     ((uint32_t)depth << 19);
+                                const int c = dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth);
+                                far1 = !A.per_node && c >= kAlphaFar;
+                                if (far1) {
+                                    fkey = alpha_key(dx, dy, dz, c, orient, A.log2m);
+                                    fbeta = h.content ? beta_of(dx, dy, dz, h.i) : 0.0f;
+                                    fvk = __int_as_float(pw);
                                 }
                             }
                         }
@@ -960,7 +1015,7 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
             t0 = __shfl(t0, 0) + lo;
             if (t0 >= hi) break;
             const int t1 = t0 + A.chunk < hi ? t0 + A.chunk : hi;
-            for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE>(A, ti, lds, tab8, thick);
+            for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE, true>(A, ti, lds, tab8, thick);
         }
     }
 }
@@ -977,7 +1032,7 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
 constexpr int kMaxLevels = 16;
 
 struct CoopLayout {
-    int bins, flgm, flgt, fr0, fr1, ctl, part, queues, total;
+    int bins, flgm, flgt, fr0, fr1, ctl, part, queues, qmeta, total;
 };
 
 __host__ __device__ inline CoopLayout coop_layout(int npix, int bp, int fcap, int waves) {
@@ -991,12 +1046,14 @@ __host__ __device__ inline CoopLayout coop_layout(int npix, int bp, int fcap, in
     L.ctl = o;   o += (2 * kMaxLevels + 4) * 4;   // grab[level], count[level], target
     L.part = o;  o += 4 * 4 * 4;                  // partial sums of up to 4 ray waves
     L.queues = o; o += waves * 2 * kQueue * 4;
+    L.qmeta = o;  o += waves * kFarQ * 12;
     L.total = (o + 15) & ~15;
     return L;
 }
 
-__device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLayout &L, int fcap,
+__device__ void coop_target(const TraceArgs &A0, int ti, char *lds, const CoopLayout &L, int fcap,
                             const uint8_t *tab8, float4 *thick) {
+    const TraceArgs &A = args_at<true>(A0); // the kernel's only argument
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     float *bins = reinterpret_cast<float *>(lds + L.bins);
     uint32_t *flgm = reinterpret_cast<uint32_t *>(lds + L.flgm);
@@ -1007,6 +1064,9 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
     float *part = reinterpret_cast<float *>(lds + L.part);
     int *qnode = reinterpret_cast<int *>(lds + L.queues) + wv * 2 * kQueue;
     uint32_t *qpk = reinterpret_cast<uint32_t *>(qnode + kQueue);
+    int *qkey = reinterpret_cast<int *>(lds + L.qmeta) + wv * 3 * kFarQ;
+    float *qbeta = reinterpret_cast<float *>(qkey + kFarQ);
+    float *qvk = qbeta + kFarQ;
     const int tid = A.targets[ti];
     const int4 tr = A.nodes[tid];
     const int tx = tr.x & 0xffff, ty = tr.y & 0xffff, tz = tr.z;
@@ -1046,6 +1106,7 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
             const uint32_t *Fc = (lev & 1) ? fr1 : fr0;
             uint32_t *Fn = (lev & 1) ? fr0 : fr1;
             for (;;) {
+                const TraceArgs &A = args_at<true>(A0);
                 // 16 ranges per grab: every lane tests up to two nodes, one from each half
                 int c = 0;
                 if (lane == 0) c = atomicAdd(grab + lev, 16);
@@ -1061,8 +1122,11 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
                         const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
                         bool open = false, enq = false, far1 = false;
                         uint32_t push = 0, pk = 0;
+                        int fkey = 0;
+                        float fbeta = 0.0f, fvk = 0.0f;
                         if (node >= 0)
-                            visit_node<false>(A, node, T, G, n_b, n_h, n_open, open, push, enq, pk, far1);
+                            visit_node<false>(A, node, T, G, n_b, n_h, n_open, open, push, enq, pk, far1, fkey, fbeta,
+                                              fvk);
                         const uint64_t bal = __ballot(open);
                         const int npush = __builtin_popcountll(bal);
                         if (npush) {
@@ -1079,14 +1143,19 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
                                                  : kQueue - 1 - qs - __builtin_popcountll(gb & below);
                             qnode[qp] = node;
                             qpk[qp] = pk;
+                            if (far1) {
+                                qkey[qp] = fkey;
+                                qbeta[qp] = fbeta;
+                                qvk[qp] = fvk;
+                            }
                         }
                         qf += __builtin_popcountll(fb);
                         qs += __builtin_popcountll(gb);
                         wave_sync();
                         if (qf >= 64) {
                             const int e = qf - 64 + lane;
-                            map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick,
-                                                        flgt);
+                            map_queue<true, true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm,
+                                                              thick, flgt, qkey, qbeta, qvk);
                             qf -= 64;
                             wave_sync();
                         }
@@ -1109,7 +1178,8 @@ __device__ void coop_target(const TraceArgs &A, int ti, char *lds, const CoopLay
             if (qf > 0) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = lane < nq ? qf - nq + lane : -1;
-                map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt);
+                map_queue<true, true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt,
+                                                  qkey, qbeta, qvk);
                 qf -= nq;
                 wave_sync();
             }
