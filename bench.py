@@ -91,6 +91,76 @@ def train_network(T, ctx, name, steps):
     return mlp, losses
 
 
+def interior_states(n, seed):
+    """Log-uniform (rho, u_rad, T_gas) on the device (the dust solve's interior states)."""
+    import torch
+    import workloads as W
+    smp = W.dust_samples(n, seed=seed).astype(np.float32)
+    return tuple(torch.from_numpy(np.ascontiguousarray(smp[:, k])).cuda() for k in range(3))
+
+
+def train_interior(T, ctx, units, steps):
+    """Guess network for interior states, trained on a separate draw (untimed setup)."""
+    from paper_2204_09072_amd.guess import train_guess
+    from paper_2204_09072_amd.run import dust
+    r, u, t = interior_states(200_000, seed=31)
+    lab, _ = dust(ctx, r, u, t, units[0], units[1])
+    ctx.sync()
+    t0 = time.perf_counter()
+    mlp, losses = train_guess(ctx, r.cpu().numpy(), u.cpu().numpy(), t.cpu().numpy(), lab.cpu().numpy(),
+                              steps=steps, batch=8192, log_every=max(steps // 5, 1))
+    return mlp, {"steps": steps, "seconds": round(time.perf_counter() - t0, 2),
+                 "loss": [round(l, 6) for _, l in losses]}
+
+
+DUST_VARIANTS = (("learned", True, {}), ("learned_linear_newton", True, dict(linear=True)),
+                 ("plain", False, dict(start=1, linear=True, max_iter=250)),
+                 ("plain_log_newton", False, dict(start=1)), ("secant_log_newton", False, dict(start=0)))
+
+
+def dust_compare(T, ctx, mlp, rho, u_rad, t_gas, units, reps=20):
+    """Every start on the same fields with the same stopping rule: time (HIP events, the
+    network's inference included for the learned starts), Newton steps, solutions."""
+    import torch
+    n = rho.numel()
+    stats, sol = {}, {}
+    for name, learned, kw in DUST_VARIANTS:
+        m = mlp if learned else None
+        out = torch.empty(n, device="cuda")
+        it = torch.empty(n, dtype=torch.uint8, device="cuda")
+        dpv = T.dust_params(units[0], units[1], **kw)
+        T.dust_equilibrium(ctx, rho, u_rad, t_gas, dpv, out, it, m)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            T.dust_equilibrium(ctx, rho, u_rad, t_gas, dpv, out, it, m)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_v = e0.elapsed_time(e1) / reps
+        itf = it.float()
+        stats[name] = {"ms": round(ms_v, 4), "solves_per_s": n / (ms_v / 1000.0),
+                       "mean_iters": round(float(itf.mean().item()), 3), "max_iters": int(it.max().item())}
+        sol[name] = out.cpu().numpy()
+    ref = sol["plain"]
+    for name in stats:
+        stats[name]["max_rel_diff_vs_plain"] = float(np.max(np.abs(sol[name] - ref) / ref))
+    return stats, sol
+
+
+def dust_summary(stats):
+    best_analytic = min(stats[k]["ms"] for k in stats if not k.startswith("learned"))
+    best_learned = min(stats[k]["ms"] for k in stats if k.startswith("learned"))
+    return {"unit": "T_dust solves/s",
+            "learned_solves_per_s": stats["learned"]["solves_per_s"],
+            "plain_solves_per_s": stats["plain"]["solves_per_s"],
+            "speedup_learned_over_plain": round(stats["plain"]["ms"] / stats["learned"]["ms"], 3),
+            "speedup_best_learned_over_plain": round(stats["plain"]["ms"] / best_learned, 3),
+            "speedup_learned_over_best_analytic_start": round(best_analytic / stats["learned"]["ms"], 3),
+            "variants": stats,
+            "stop_rule": "Newton step |dT| <= 1e-6 T (taken before the bracket test) or bracket width "
+                         "<= 1e-6 T, bracket-safeguarded"}
+
+
 def cpu_baseline(w, n_pix, stride, u_rad=None, gpu_t_dust=None):
     """FP64 oracle on the host cores: tree, every `stride`-th target, force and dust."""
     import oracle
@@ -417,41 +487,22 @@ def main():
     dust = None
     dust_T = {}
     if w.cgs:
-        variants = {"learned": (mlp, {}),
-                    "plain": (None, dict(start=1, linear=True, max_iter=250)),
-                    "plain_log_newton": (None, dict(start=1)),
-                    "secant_log_newton": (None, dict(start=0))}
-        stats = {}
-        for name, (m, kw) in variants.items():
-            out = torch.empty(n, device="cuda")
-            it = torch.empty(n, dtype=torch.uint8, device="cuda")
-            dpv = T.dust_params(w.units[0], w.units[1], **kw)
-            T.dust_equilibrium(ctx, dev["rho"], U, dev["t_gas"], dpv, out, it, m)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            reps = 20
-            e0.record()
-            for _ in range(reps):
-                T.dust_equilibrium(ctx, dev["rho"], U, dev["t_gas"], dpv, out, it, m)
-            e1.record()
-            torch.cuda.synchronize()
-            ms_v = e0.elapsed_time(e1) / reps
-            itf = it.float()
-            stats[name] = {"ms": round(ms_v, 4), "solves_per_s": n / (ms_v / 1000.0),
-                           "mean_iters": round(float(itf.mean().item()), 3),
-                           "max_iters": int(it.max().item())}
-            dust_T[name] = out.cpu().numpy()
-        ref = dust_T["plain"]
-        for name in stats:
-            stats[name]["max_rel_diff_vs_plain"] = float(np.max(np.abs(dust_T[name] - ref) / ref))
-        best_analytic = min(stats[k]["ms"] for k in stats if k != "learned")
-        dust = {"unit": "T_dust solves/s",
-                "learned_solves_per_s": stats["learned"]["solves_per_s"],
-                "plain_solves_per_s": stats["plain"]["solves_per_s"],
-                "speedup_learned_over_plain": round(stats["plain"]["ms"] / stats["learned"]["ms"], 3),
-                "speedup_learned_over_best_analytic_start": round(best_analytic / stats["learned"]["ms"], 3),
-                "variants": stats,
-                "stop_rule": "|dT| <= 1e-6 T or bracket width <= 1e-6 T, bracket-safeguarded",
-                "network": train_info}
+        stats, dust_T = dust_compare(T, ctx, mlp, dev["rho"], U, dev["t_gas"], w.units)
+        dust = dust_summary(stats)
+        dust["network"] = train_info
+        # states inside the bracket (log-uniform over the dense-cloud range), where a guess
+        # can help: in the core most cells have T_dust at a bracket end (T_gas or T_J)
+        log("dust on interior states ...")
+        t0 = time.perf_counter()
+        mlp_i, info_i = train_interior(T, ctx, w.units, args.train_steps)
+        ri, ui, ti = interior_states(n, seed=32)
+        st_i, _ = dust_compare(T, ctx, mlp_i, ri, ui, ti, w.units)
+        dust["interior_states"] = dict(dust_summary(st_i), network=info_i,
+                                       states="%d log-uniform (rho 1e-24..1e-14 g/cm^3, u_rad 1e-16..1e-6 "
+                                              "erg/cm^3, T_gas 5..2000 K), network trained on another "
+                                              "draw of 200 000" % n,
+                                       seconds=round(time.perf_counter() - t0, 2))
+        mlp_i.free()
 
     base = None
     if not args.no_cpu_baseline:

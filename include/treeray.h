@@ -223,7 +223,7 @@ int tr_dust_fixed_point(tr_ctx *ctx, const tr_grid *grid, const float *rho, cons
 
 /* Guess network for the dust equilibrium: inputs (log10 rho, log10 u_rad, log10 T_gas)
  * normalised as (v - shift) * scale, output log10 T_d = y / out_scale + out_shift;
- * 3 -> 64 -> 64 -> 1 with tanh hidden layers; BF16 MFMA with FP32 accumulation.
+ * 3 -> 64 -> 64 -> 1 with ReLU hidden layers; BF16 MFMA with FP32 accumulation.
  * Parameters (HOST float, n = tr_mlp_n_params()) in the order
  * W1[64][3] b1[64] W2[64][64] b2[64] W3[64] b3. */
 int tr_mlp_n_params(void);

@@ -949,7 +949,8 @@ void or_dust_eq(int64_t n, const double *rho, const double *u_rad, const double 
 }
 
 /* ------------------------------------------------------------------------------------
- * MLP 3 -> H -> H -> 1 with tanh hidden activations (guess of the equilibrium solve)
+ * MLP 3 -> H -> H -> 1 with ReLU hidden activations, max(a, 0) (guess of the equilibrium
+ * solve; the network is not part of the paper, its architecture is this library's choice)
  * ---------------------------------------------------------------------------------- */
 static double to_bf16(double v) {
     float f = (float)v;
@@ -982,14 +983,14 @@ double or_mlp(int H, const double *prm, int64_t n, const double *x, const double
         for (int j = 0; j < H; ++j) {
             double a = b1[j];
             for (int k = 0; k < 3; ++k) a += W1[3 * j + k] * xi[k];
-            h1[j] = tanh(a);
+            h1[j] = a > 0.0 ? a : 0.0;
         }
         double h1r[1024];
         for (int j = 0; j < H; ++j) h1r[j] = rb ? to_bf16(h1[j]) : h1[j];
         for (int j = 0; j < H; ++j) {
             double a = b2[j];
             for (int k = 0; k < H; ++k) a += W2[H * j + k] * h1r[k];
-            h2[j] = tanh(a);
+            h2[j] = a > 0.0 ? a : 0.0;
         }
         double h2r[1024];
         for (int j = 0; j < H; ++j) h2r[j] = rb ? to_bf16(h2[j]) : h2[j];
@@ -1003,7 +1004,7 @@ double or_mlp(int H, const double *prm, int64_t n, const double *x, const double
             gb3[0] += dy;
             for (int k = 0; k < H; ++k) {
                 g3[k] += dy * h2r[k];
-                d2[k] = dy * W3[k] * (1.0 - h2[k] * h2[k]);
+                d2[k] = h2[k] > 0.0 ? dy * W3[k] : 0.0; /* ReLU passes the gradient where active */
             }
             for (int j = 0; j < H; ++j) {
                 gb2[j] += d2[j];
@@ -1012,7 +1013,7 @@ double or_mlp(int H, const double *prm, int64_t n, const double *x, const double
             for (int k = 0; k < H; ++k) {
                 double a = 0.0;
                 for (int j = 0; j < H; ++j) a += W2[H * j + k] * d2[j];
-                d1[k] = a * (1.0 - h1[k] * h1[k]);
+                d1[k] = h1[k] > 0.0 ? a : 0.0;
             }
             for (int j = 0; j < H; ++j) {
                 gb1[j] += d1[j];

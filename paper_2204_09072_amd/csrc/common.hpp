@@ -18,9 +18,12 @@ struct RayTable {
     int n_side = 0, cube_m = 0;
     int16_t *table = nullptr; // [6][M][M] pixel ids
     float4 *dirs = nullptr;   // [npix] unit vectors
-    // tabulated angular kernel: [6][M][M][15 distance classes] int4 entries (pixels 0-1,
-    // pixels 2-3, counts of 64, more-than-4-pixels flag)
-    int4 *alpha = nullptr;
+    // tabulated angular kernel: [6][M][M][classes 6 .. alpha_c1 - 1] packed 64-bit entries
+    // (4 pixels of 10 bits, 3 counts of 7 bits out of 64, the 4th by difference, and the
+    // more-than-4-pixels flag at bit 61); classes from alpha_c1 on hold the direction cell's
+    // own pixel only and are read from the pixel table
+    unsigned long long *alpha = nullptr;
+    int alpha_c1 = 21;
 };
 
 struct tr_ctx {

@@ -103,6 +103,13 @@ __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
                 const float wv = wf(T, dw);
                 if (wv < K) lo = T; else hi = T;
                 float Tn = LOG ? T * __expf(-__logf(wv / K) * wv / (T * dw)) : T - (wv - K) / dw;
+                // a Newton step within tol: T is at the root to working precision.  Taken
+                // before the bracket test, since a step below FP32 resolution lands on the
+                // bracket end just moved to T and would otherwise be replaced by bisection.
+                if (fabsf(Tn - T) <= A.tol * T) {
+                    if (Tn > lo && Tn < hi) T = Tn;
+                    break;
+                }
                 if (!(Tn > lo && Tn < hi)) Tn = 0.5f * (lo + hi);
                 const bool conv = fabsf(Tn - T) <= A.tol * Tn || hi - lo <= A.tol * hi;
                 T = Tn;

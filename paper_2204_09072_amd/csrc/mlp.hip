@@ -1,14 +1,24 @@
-// Guess network for the dust-equilibrium solve: training and inference on the matrix
-// cores (bfloat16 operands, FP32 accumulation).
+// Guess network for the dust-equilibrium solve (3 -> 64 -> 64 -> 1, ReLU hidden layers):
+// training and inference on the matrix cores (bfloat16 operands, FP32 accumulation).
 //
-// One wavefront handles 32 samples at a time.  The hidden layer products that are real
-// matrix products run on v_mfma_f32_32x32x8bf16_1k:
+// One wavefront handles 32 samples at a time, on v_mfma_f32_32x32x8bf16_1k.
+// 32x32x8 operand layout: lane l holds A[l%32][4(l/32)+0..3] and B[4(l/32)+0..3][l%32];
+// the 16 accumulators of lane l are C[8(v/4) + 4(l/32) + v%4][l%32], v = 0..15.
+//
+// Training (k_mlp_train), with the hidden activations staged in LDS:
 //   forward   a2[s][n]  = sum_i h1[s][i] W2[n][i]          (32 x 64 x 64)
 //   backward  dh1[s][i] = sum_n da2[s][n] W2[n][i]         (32 x 64 x 64)
 //             gW2[n][i] += sum_s da2[s][n] h1[s][i]        (64 x 64 x 32, kept in registers)
-// The 3-wide input layer and the 1-wide output layer are per-lane dot products.
-// 32x32x8 operand layout: lane l holds A[l%32][4(l/32)+0..3] and B[4(l/32)+0..3][l%32];
-// the 16 accumulators of lane l are C[8(v/4) + 4(l/32) + v%4][l%32], v = 0..15.
+// and the 3-wide input and 1-wide output layers as per-lane dot products.
+//
+// Inference (k_mlp_infer) keeps everything in registers by working on transposed
+// products, hidden units as rows and samples as columns:
+//   a1[n][s] = sum_k [W1 | b1][n][k] [x; 1][k][s]          (K = 3 inputs + bias, padded to 8)
+//   a2[n][s] = sum_k W2[n][k] h1[k][s] + b2[n]             (bias as one more K step)
+// The accumulators of the first product are, lane for lane, the B operands of the second
+// (rows 8 kk + 4(l/32) + j of column l%32), so h1 never leaves the registers; the output
+// y[s] = w3 . h2[:, s] + b3 is a per-lane sum over the lane's 32 rows plus one exchange
+// between the two half-waves.
 #include <cmath>
 
 #include "mlp.hpp"
@@ -29,7 +39,7 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-enum Mode { TRAIN = 0, FORWARD = 1, GUESS = 2 };
+enum Mode { FORWARD = 1, GUESS = 2 };
 
 struct MlpArgs {
     int64_t n;
@@ -51,8 +61,7 @@ struct WaveLds {
     float dy[S];
 };
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
+__global__ __launch_bounds__(256) void k_mlp_train(MlpArgs A) {
     __shared__ uint16_t w2[H * LD];   // W2[n][i]
     __shared__ uint16_t w2t[H * LD];  // W2[n][i] stored as [i][n]
     __shared__ float w1[3 * H], b1[H], b2[H], w3[H];
@@ -71,8 +80,7 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
         b2[k] = bf16_val(bf16_bits(A.p[MLP_OFF_B2 + k]));
         w3[k] = bf16_val(bf16_bits(A.p[MLP_OFF_W3 + k]));
     }
-    if (MODE == TRAIN)
-        for (int k = tid; k < MLP_NPARAM; k += 256) gacc[k] = 0.0f;
+    for (int k = tid; k < MLP_NPARAM; k += 256) gacc[k] = 0.0f;
     __syncthreads();
     const float b3 = bf16_val(bf16_bits(A.p[MLP_OFF_B3]));
     WaveLds &L = wl[wv];
@@ -97,16 +105,10 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
             float x0 = 0, x1 = 0, x2 = 0, t = 0;
             if (lane < cnt) {
                 const int64_t s = s0 + lane;
-                if (MODE == GUESS) {
-                    x0 = (log10f(fmaxf(A.rho[s], 1e-37f)) - A.shift[0]) * A.scale[0];
-                    x1 = (log10f(fmaxf(A.u_rad[s], 1e-37f)) - A.shift[1]) * A.scale[1];
-                    x2 = (log10f(fmaxf(A.t_gas[s], 1e-37f)) - A.shift[2]) * A.scale[2];
-                } else {
-                    x0 = A.x[3 * s];
-                    x1 = A.x[3 * s + 1];
-                    x2 = A.x[3 * s + 2];
-                }
-                if (MODE == TRAIN) t = A.y[s];
+                x0 = A.x[3 * s];
+                x1 = A.x[3 * s + 1];
+                x2 = A.x[3 * s + 2];
+                t = A.y[s];
             }
             L.xs[lane][0] = bf16_val(bf16_bits(x0));
             L.xs[lane][1] = bf16_val(bf16_bits(x1));
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
             const float wa = w1[3 * j], wb = w1[3 * j + 1], wc = w1[3 * j + 2], bj = b1[j];
             for (int s = 0; s < S; ++s) {
                 const float a = bj + wa * L.xs[s][0] + wb * L.xs[s][1] + wc * L.xs[s][2];
-                L.h1[s * LD + j] = bf16_bits(tanh_fast(a));
+                L.h1[s * LD + j] = bf16_bits(a > 0.0f ? a : 0.0f);
             }
         }
         __builtin_amdgcn_s_waitcnt(0xc07f);
@@ -150,46 +152,12 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
             const int n = 32 * tn + col;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                h2[tn][v] = tanh_fast(acc[tn][v] + b2[n]);
+                const float a2 = acc[tn][v] + b2[n];
+                h2[tn][v] = a2 > 0.0f ? a2 : 0.0f;
                 yp[v] += w3[n] * bf16_val(bf16_bits(h2[tn][v]));
             }
         }
         // rows held by this lane: s = 8 (v/4) + 4 half + v%4
-        if (MODE != TRAIN) {
-            // sum over the 32 lanes of a half-wave by halving exchanges: after the steps
-            // over lane bits 4, 3, 2, 1 (8 + 4 + 2 + 1 shuffles) and a last one over bit
-            // 0, lane l holds the full sum of row v = 8 b4 + 4 b3 + 2 b2 + b1, b_k being
-            // bit k of the lane
-            float r8[8], r4[4], r2[2], r1;
-            const bool k4 = col & 16, k3 = col & 8, k2 = col & 4, k1 = col & 2;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float keep = k4 ? yp[j + 8] : yp[j], send = k4 ? yp[j] : yp[j + 8];
-                r8[j] = keep + __shfl_xor(send, 16);
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float keep = k3 ? r8[j + 4] : r8[j], send = k3 ? r8[j] : r8[j + 4];
-                r4[j] = keep + __shfl_xor(send, 8);
-            }
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const float keep = k2 ? r4[j + 2] : r4[j], send = k2 ? r4[j] : r4[j + 2];
-                r2[j] = keep + __shfl_xor(send, 4);
-            }
-            {
-                const float keep = k1 ? r2[1] : r2[0], send = k1 ? r2[0] : r2[1];
-                r1 = keep + __shfl_xor(send, 2);
-            }
-            r1 += __shfl_xor(r1, 1);
-            const int v = (k4 ? 8 : 0) + (k3 ? 4 : 0) + (k2 ? 2 : 0) + (k1 ? 1 : 0);
-            const int s = 8 * (v >> 2) + 4 * half + (v & 3);
-            if ((col & 1) == 0 && s < cnt) {
-                const float yv = r1 + b3;
-                A.out[s0 + s] = MODE == GUESS ? exp10f(yv / A.out_scale + A.out_shift) : yv;
-            }
-            continue;
-        }
 #pragma unroll
         for (int v = 0; v < 16; ++v)
             for (int o = 1; o < 32; o <<= 1) yp[v] += __shfl_xor(yp[v], o);
@@ -204,14 +172,14 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
                 gb3 += dy[v];
             }
         }
-        // backward through the output layer and the second tanh
+        // backward through the output layer and the second ReLU
 #pragma unroll
         for (int tn = 0; tn < 2; ++tn) {
             const int n = 32 * tn + col;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int s = 8 * (v >> 2) + 4 * half + (v & 3);
-                const float da = dy[v] * w3[n] * (1.0f - h2[tn][v] * h2[tn][v]);
+                const float da = h2[tn][v] > 0.0f ? dy[v] * w3[n] : 0.0f;
                 gw3[tn] += dy[v] * bf16_val(bf16_bits(h2[tn][v]));
                 gb2[tn] += da;
                 L.da2[s * LD + n] = bf16_bits(da);
@@ -235,7 +203,7 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
                     }
                     gw2[tn][ti] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, gw2[tn][ti], 0, 0, 0);
                 }
-        // dh1 = da2 W2, then through the first tanh to the input layer's gradients
+        // dh1 = da2 W2, then through the first ReLU to the input layer's gradients
 #pragma unroll
         for (int ti = 0; ti < 2; ++ti) {
             f16v d;
@@ -253,8 +221,8 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int s = 8 * (v >> 2) + 4 * half + (v & 3);
-                const float h = tanh_fast(bi + wa * L.xs[s][0] + wb * L.xs[s][1] + wc * L.xs[s][2]);
-                const float da1 = d[v] * (1.0f - h * h);
+                const float a1 = bi + wa * L.xs[s][0] + wb * L.xs[s][1] + wc * L.xs[s][2];
+                const float da1 = a1 > 0.0f ? d[v] : 0.0f;
                 gb1[ti] += da1;
                 gw1[ti][0] += da1 * L.xs[s][0];
                 gw1[ti][1] += da1 * L.xs[s][1];
@@ -264,7 +232,6 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
     }
-    if (MODE != TRAIN) return;
     // block reduction of the gradients in LDS, then one global add per parameter
 #pragma unroll
     for (int tn = 0; tn < 2; ++tn)
@@ -292,6 +259,129 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs A) {
     if (col == 0) atomicAdd(A.loss, lsum * A.inv_n);
 }
 
+// two floats to packed bfloat16 (round to nearest even, v_cvt_pk_bf16_f32)
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+    const f2v x = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf2v));
+}
+__device__ __forceinline__ sh4 sh4_of(uint32_t lo, uint32_t hi) {
+    const u2v v = {lo, hi};
+    return __builtin_bit_cast(sh4, v);
+}
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf8v bf8_of(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    const u4v v = {a, b, c, d};
+    return __builtin_bit_cast(bf8v, v);
+}
+// max(x, 0) in one integer max: negative floats have negative bit patterns
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+// eight accumulators v0 .. v0 + 7 of a tile, ReLU'd and packed as a K = 16 operand
+__device__ __forceinline__ bf8v relu_pack8(const f16v &a, int v0) {
+    return bf8_of(pk_bf16(relu(a[v0]), relu(a[v0 + 1])), pk_bf16(relu(a[v0 + 2]), relu(a[v0 + 3])),
+                  pk_bf16(relu(a[v0 + 4]), relu(a[v0 + 5])), pk_bf16(relu(a[v0 + 6]), relu(a[v0 + 7])));
+}
+
+// Inference, 32 samples per wave step, all operands in registers (layouts in the header).
+// The second product runs on v_mfma_f32_32x32x16_bf16 (K = 16 per instruction): lane l
+// contributes 8 K-slots, A and B slot for slot, and a contraction may visit K in any
+// order, so K-block kk takes accumulators v = 8 (kk % 2) + j of first-layer tile kk / 2 as
+// its B slots and the matching columns of W2 as its A slots.  The next step's inputs are
+// loaded while the current step computes.  The output layer is a third product,
+// y[s] = sum_k w3[k] h2[k][s], with w3 as row 0 of its A operand and h2 packed exactly as
+// h1 was; row 0 of the result is accumulator 0 of lanes 0..31.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs A) {
+    const int lane = threadIdx.x & 63, col = lane & 31, half = lane >> 5;
+    const int wave = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    const int nwave = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
+    const float *W1 = A.p, *B1 = A.p + MLP_OFF_B1, *W2 = A.p + MLP_OFF_W2, *B2 = A.p + MLP_OFF_B2,
+                *W3 = A.p + MLP_OFF_W3;
+    // weights as operands: [W1 | b1] and [b2] (half-wave 0 holds k = 0..3, half-wave 1 the
+    // zero padding), W2 rows 32 t + col, and w3 in row 0 (lanes 0 and 32) with the same
+    // slot order as W2's columns
+    sh4 aw1[2], ab2[2];
+    bf8v aw2[2][H / 16], aw3[H / 16];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int n = 32 * t + col;
+        aw1[t] = half == 0 ? sh4_of(pk_bf16(W1[3 * n], W1[3 * n + 1]), pk_bf16(W1[3 * n + 2], B1[n]))
+                           : sh4_of(0u, 0u);
+        ab2[t] = half == 0 ? sh4_of(pk_bf16(B2[n], 0.0f), 0u) : sh4_of(0u, 0u);
+#pragma unroll
+        for (int kk = 0; kk < H / 16; ++kk) {
+            // slot j <-> hidden unit 32 (kk / 2) + 16 (kk % 2) + 8 (j / 4) + 4 half + j % 4
+            const float *w = W2 + H * n + 32 * (kk >> 1) + 16 * (kk & 1) + 4 * half;
+            aw2[t][kk] = bf8_of(pk_bf16(w[0], w[1]), pk_bf16(w[2], w[3]), pk_bf16(w[8], w[9]), pk_bf16(w[10], w[11]));
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < H / 16; ++kk) {
+        const float *w = W3 + 32 * (kk >> 1) + 16 * (kk & 1) + 4 * half;
+        aw3[kk] = col == 0 ? bf8_of(pk_bf16(w[0], w[1]), pk_bf16(w[2], w[3]), pk_bf16(w[8], w[9]), pk_bf16(w[10], w[11]))
+                           : bf8_of(0u, 0u, 0u, 0u);
+    }
+    const float b3 = bf16_val(bf16_bits(A.p[MLP_OFF_B3]));
+    const sh4 bone = half == 0 ? sh4_of(pk_bf16(1.0f, 0.0f), 0u) : sh4_of(0u, 0u);
+    const f16v zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t nchunk = (A.n + S - 1) / S;
+    // raw inputs of sample ch * 32 + col (half-wave 0 only)
+    auto load = [&](int64_t ch, float &x0, float &x1, float &x2) {
+        const int64_t s = ch * S + col;
+        x0 = x1 = x2 = 1.0f;
+        if (half == 0 && ch < nchunk && s < A.n) {
+            if (MODE == GUESS) {
+                x0 = A.rho[s]; x1 = A.u_rad[s]; x2 = A.t_gas[s];
+            } else {
+                x0 = A.x[3 * s]; x1 = A.x[3 * s + 1]; x2 = A.x[3 * s + 2];
+            }
+        }
+    };
+    float r0, r1, r2;
+    load(wave, r0, r1, r2);
+    for (int64_t ch = wave; ch < nchunk; ch += nwave) {
+        const int64_t s = ch * S + col;
+        const bool live = half == 0 && s < A.n;
+        float x0 = r0, x1 = r1, x2 = r2;
+        load(ch + nwave, r0, r1, r2);
+        if (MODE == GUESS) {
+            // hardware logarithm (about 1 ulp): far finer than the inputs' bfloat16 rounding
+            x0 = (__log10f(fmaxf(x0, 1e-37f)) - A.shift[0]) * A.scale[0];
+            x1 = (__log10f(fmaxf(x1, 1e-37f)) - A.shift[1]) * A.scale[1];
+            x2 = (__log10f(fmaxf(x2, 1e-37f)) - A.shift[2]) * A.scale[2];
+        }
+        // B operand of the first product: column s = (x0, x1, x2, 1) in half-wave 0
+        const sh4 bx = live ? sh4_of(pk_bf16(x0, x1), pk_bf16(x2, 1.0f)) : sh4_of(0u, 0u);
+        f16v a1[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) a1[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw1[t], bx, zero, 0, 0, 0);
+        // h1 = ReLU(a1) in bfloat16: K-block kk holds accumulators 8 (kk % 2) + 0..7 of
+        // tile kk / 2 (rows 16 (kk % 2) + 8 (j / 4) + 4 half + j % 4)
+        bf8v bh[H / 16];
+#pragma unroll
+        for (int kk = 0; kk < H / 16; ++kk) bh[kk] = relu_pack8(a1[kk >> 1], 8 * (kk & 1));
+        f16v a2[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            a2[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ab2[t], bone, zero, 0, 0, 0);
+#pragma unroll
+            for (int kk = 0; kk < H / 16; ++kk)
+                a2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw2[t][kk], bh[kk], a2[t], 0, 0, 0);
+        }
+        f16v a3 = zero;
+#pragma unroll
+        for (int kk = 0; kk < H / 16; ++kk)
+            a3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw3[kk], relu_pack8(a2[kk >> 1], 8 * (kk & 1)), a3, 0, 0, 0);
+        if (live) {
+            const float yv = a3[0] + b3;
+            A.out[s] = MODE == GUESS ? __exp10f(yv / A.out_scale + A.out_shift) : yv;
+        }
+    }
+}
+
 __global__ void k_fill(float *p, int n, float v) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -316,10 +406,12 @@ __global__ void k_round(const float *p, float *wq, int n) {
     if (i < n) wq[i] = bf16_round(p[i]);
 }
 
-int grid_for(tr_ctx *ctx, int64_t n) {
+// blocks of 4 waves for n samples, at most per_cu blocks per compute unit (the kernels
+// loop over 32-sample steps)
+int grid_for(tr_ctx *ctx, int64_t n, int per_cu = 4) {
     const int64_t waves = (n + S - 1) / S;
     int64_t blocks = (waves + 3) / 4;
-    const int64_t cap = (int64_t)ctx->n_cu * 4;
+    const int64_t cap = (int64_t)ctx->n_cu * per_cu;
     if (blocks > cap) blocks = cap;
     return (int)(blocks < 1 ? 1 : blocks);
 }
@@ -344,7 +436,7 @@ int mlp_guess(tr_ctx *ctx, const tr_mlp *m, int64_t n, const float *rho, const f
               const float *t_gas, float *guess) {
     MlpArgs A = base_args(m, n);
     A.rho = rho; A.u_rad = u_rad; A.t_gas = t_gas; A.out = guess;
-    k_mlp<GUESS><<<grid_for(ctx, n), 256, 0, ctx->stream>>>(A);
+    k_mlp_infer<GUESS><<<grid_for(ctx, n, 3), 256, 0, ctx->stream>>>(A); // 3 waves/SIMD fit
     return hipGetLastError() == hipSuccess ? TR_OK : tr_fail(ctx, TR_EHIP, "mlp guess launch failed");
 }
 
@@ -399,7 +491,7 @@ extern "C" int tr_mlp_forward(tr_ctx *ctx, const tr_mlp *m, int64_t n, const flo
     if (n == 0) return TR_OK;
     MlpArgs A = base_args(m, n);
     A.x = x; A.out = y;
-    k_mlp<FORWARD><<<grid_for(ctx, n), 256, 0, ctx->stream>>>(A);
+    k_mlp_infer<FORWARD><<<grid_for(ctx, n, 3), 256, 0, ctx->stream>>>(A);
     return hipGetLastError() == hipSuccess ? TR_OK : tr_fail(ctx, TR_EHIP, "mlp forward launch failed");
 }
 
@@ -411,7 +503,7 @@ extern "C" int tr_mlp_grad(tr_ctx *ctx, const tr_mlp *m, int64_t n, const float 
     k_fill<<<1, 64, 0, ctx->stream>>>(loss, 1, 0.0f);
     MlpArgs A = base_args(m, n);
     A.x = x; A.y = y; A.grad = grad; A.loss = loss;
-    k_mlp<TRAIN><<<grid_for(ctx, n), 256, 0, ctx->stream>>>(A);
+    k_mlp_train<<<grid_for(ctx, n), 256, 0, ctx->stream>>>(A);
     return hipGetLastError() == hipSuccess ? TR_OK : tr_fail(ctx, TR_EHIP, "mlp grad launch failed");
 }
 

@@ -1,4 +1,4 @@
-// Guess network of the dust-equilibrium solve: 3 -> 64 -> 64 -> 1, tanh hidden layers.
+// Guess network of the dust-equilibrium solve: 3 -> 64 -> 64 -> 1, ReLU hidden layers.
 #pragma once
 #include "common.hpp"
 
@@ -23,14 +23,6 @@ struct tr_mlp {
 // temperature guesses of the network for raw (rho, u_rad, T_gas) fields, on the matrix cores
 int mlp_guess(tr_ctx *ctx, const tr_mlp *m, int64_t n, const float *rho, const float *u_rad,
               const float *t_gas, float *guess);
-
-// tanh x = 1 - 2 / (e^{2x} + 1) from the hardware exponential and reciprocal (absolute
-// error ~1e-7, far below the bfloat16 rounding of the activations); e^{2x} overflowing to
-// infinity gives 1 and underflowing to 0 gives -1.
-__device__ __forceinline__ float tanh_fast(float x) {
-    const float e = __expf(2.0f * x);
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
-}
 
 __device__ __forceinline__ float bf16_round(float x) {
     uint32_t u = __float_as_uint(x);

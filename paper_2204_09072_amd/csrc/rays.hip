@@ -165,7 +165,10 @@ int tr_get_table(tr_ctx *ctx, int n_side, int cube_m, RayTable **out) {
         return (int64_t)(f * M + i) * M + j;
     };
     constexpr int nclass = 15;
-    std::vector<int4> alpha(ne * nclass);
+    struct Entry {
+        int np, px[4], cnt[4];
+    };
+    std::vector<Entry> full(ne * nclass);
     for (int f = 0; f < 6; ++f) {
         const int ax = f / 2, oa = ax == 0 ? 1 : 0, ob = ax == 2 ? 1 : 2;
         for (int i = 0; i < M; ++i)
@@ -194,21 +197,43 @@ int tr_get_table(tr_ctx *ctx, int n_side, int cube_m, RayTable **out) {
                             std::swap(px[v], px[v - 1]);
                             std::swap(cnt[v], cnt[v - 1]);
                         }
-                    int4 en = make_int4(0, 0, 0, np > 4 ? 1 : 0);
-                    if (np <= 4) {
-                        int pp[4] = {0, 0, 0, 0}, cc[4] = {0, 0, 0, 0};
-                        for (int k = 0; k < np; ++k) { pp[k] = px[k]; cc[k] = cnt[k]; }
-                        en.x = (int)((uint32_t)pp[0] | ((uint32_t)pp[1] << 16));
-                        en.y = (int)((uint32_t)pp[2] | ((uint32_t)pp[3] << 16));
-                        en.z = (int)((uint32_t)cc[0] | ((uint32_t)cc[1] << 8) | ((uint32_t)cc[2] << 16) |
-                                     ((uint32_t)cc[3] << 24));
+                    Entry &en = full[(((int64_t)f * M + i) * M + j) * nclass + (c - 6)];
+                    en.np = np;
+                    for (int k = 0; k < 4; ++k) {
+                        en.px[k] = k < np && np <= 4 ? px[k] : 0;
+                        en.cnt[k] = k < np && np <= 4 ? cnt[k] : 0;
                     }
-                    alpha[(((int64_t)f * M + i) * M + j) * nclass + (c - 6)] = en;
                 }
             }
     }
-    if (hipMalloc(&rt.alpha, sizeof(int4) * alpha.size()) != hipSuccess ||
-        hipMemcpy(rt.alpha, alpha.data(), sizeof(int4) * alpha.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    // the first class from which every entry is the direction cell's own pixel alone
+    int c1 = 21;
+    for (; c1 > 6; --c1) {
+        bool own = true;
+        for (int64_t cell = 0; own && cell < ne; ++cell) {
+            const Entry &en = full[cell * nclass + (c1 - 1 - 6)];
+            own = en.np == 1 && en.px[0] == pix[cell];
+        }
+        if (!own) break;
+    }
+    const int ncls = c1 - 6;
+    std::vector<unsigned long long> packed(ne * (ncls > 0 ? ncls : 1), 0ull);
+    for (int64_t cell = 0; cell < ne; ++cell)
+        for (int c = 6; c < c1; ++c) {
+            const Entry &en = full[cell * nclass + (c - 6)];
+            unsigned long long w = 0;
+            if (en.np > 4) {
+                w = 1ull << 61;
+            } else {
+                for (int k = 0; k < 4; ++k) w |= (unsigned long long)en.px[k] << (10 * k);
+                for (int k = 0; k < 3; ++k) w |= (unsigned long long)en.cnt[k] << (40 + 7 * k);
+            }
+            packed[cell * ncls + (c - 6)] = w;
+        }
+    rt.alpha_c1 = c1;
+    if (hipMalloc(&rt.alpha, sizeof(unsigned long long) * packed.size()) != hipSuccess ||
+        hipMemcpy(rt.alpha, packed.data(), sizeof(unsigned long long) * packed.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
         hipFree(rt.table);
         hipFree(rt.dirs);
         hipFree(rt.alpha);
@@ -250,16 +275,35 @@ extern "C" int tr_alpha_table(tr_ctx *ctx, int n_side, int cube_m, int32_t *out)
     RayTable *rt = nullptr;
     int rc = tr_get_table(ctx, n_side, cube_m, &rt);
     if (rc) return rc;
-    const int64_t nk = 6 * (int64_t)cube_m * cube_m * 15;
-    std::vector<int4> a(nk);
-    TR_HIP(ctx, hipMemcpyAsync(a.data(), rt->alpha, sizeof(int4) * nk, hipMemcpyDeviceToHost, ctx->stream));
+    const int64_t ne = 6 * (int64_t)cube_m * cube_m;
+    const int c1 = rt->alpha_c1, ncls = c1 - 6;
+    std::vector<unsigned long long> a(ne * (ncls > 0 ? ncls : 1));
+    std::vector<int16_t> pix(ne);
+    TR_HIP(ctx, hipMemcpyAsync(a.data(), rt->alpha, sizeof(unsigned long long) * a.size(), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    TR_HIP(ctx, hipMemcpyAsync(pix.data(), rt->table, sizeof(int16_t) * ne, hipMemcpyDeviceToHost, ctx->stream));
     TR_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (int64_t k = 0; k < nk; ++k) {
-        int32_t *o = out + 9 * k;
-        o[0] = a[k].x & 0xffff; o[1] = (int32_t)((uint32_t)a[k].x >> 16);
-        o[2] = a[k].y & 0xffff; o[3] = (int32_t)((uint32_t)a[k].y >> 16);
-        for (int c = 0; c < 4; ++c) o[4 + c] = (int32_t)(((uint32_t)a[k].z >> (8 * c)) & 255u);
-        o[8] = a[k].w;
-    }
+    for (int64_t cell = 0; cell < ne; ++cell)
+        for (int c = 6; c <= 20; ++c) {
+            int32_t *o = out + 9 * (cell * 15 + (c - 6));
+            for (int k = 0; k < 9; ++k) o[k] = 0;
+            if (c >= c1) {
+                o[0] = pix[cell];
+                o[4] = 64;
+                continue;
+            }
+            const unsigned long long w = a[cell * ncls + (c - 6)];
+            if ((w >> 61) & 1ull) {
+                o[8] = 1;
+                continue;
+            }
+            for (int k = 0; k < 4; ++k) o[k] = (int32_t)((w >> (10 * k)) & 1023ull);
+            int sum = 0;
+            for (int k = 0; k < 3; ++k) {
+                o[4 + k] = (int32_t)((w >> (40 + 7 * k)) & 127ull);
+                sum += o[4 + k];
+            }
+            o[7] = 64 - sum;
+        }
     return TR_OK;
 }

@@ -49,7 +49,7 @@ struct TraceArgs {
     const float *cell_tau;
     const float *cell_src;
     const int16_t *table;
-    const int4 *alpha;     // tabulated angular kernel [6 M M][distance classes]
+    const unsigned long long *alpha; // tabulated angular kernel [6 M M][classes 6 .. alpha_c1 - 1]
     const float4 *dirs;
     int *work;
     int *err;
@@ -62,6 +62,7 @@ struct TraceArgs {
     int root_edge;
     int npix;
     int log2m;      // direction cells per face edge = 1 << log2m
+    int alpha_c1;   // first distance class served by the pixel table (the cell's own pixel)
     int n_bins;
     int bp;         // bins per pass
     int n_pass;
@@ -255,12 +256,13 @@ __device__ __forceinline__ void seg_sum_step(int rl, int rid, float &v0, float &
 
 // Tabulated angular kernel (Sec. 4.2.1): nodes at least 8 edges away (r >= 8 s) take the
 // entry of their direction cell and distance class c = floor(log2(r^2 / s^2)), 6 <= c <= 20
-// (larger classes count as 20).  Entry int4: pixels 0, 1 (x, 16 bits each), pixels 2, 3
-// (y), the four counts out of 64 (z, 8 bits each), and w != 0 when the key's sub-points
-// reach more than 4 pixels (the node then takes the per-node kernel).
+// (larger classes count as 20).  Entry: 64 bits, pixels 0..3 (10 bits each from bit 0),
+// counts 0..2 out of 64 (7 bits each from bit 40; count 3 = 64 - the others) and bit 61 set
+// when the key's sub-points reach more than 4 pixels (the node then takes the per-node
+// kernel).  From class alpha_c1 on every entry is the direction cell's own pixel alone, and
+// the pixel table serves those keys (a negative key -1 - cell).
 constexpr int kAlphaFar = 6;
 constexpr int kAlphaMax = 20;
-constexpr int kAlphaClasses = kAlphaMax - kAlphaFar + 1;
 
 // distance class c = floor(log2(r^2 / s^2)) of an offset (1/256 lattice units, r^2 > 0)
 // from a node of edge s = 2^log2s: node edges are powers of two, so s^2 = 2^(16 + 2 log2s)
@@ -271,12 +273,13 @@ __device__ __forceinline__ int dist_class(int dx, int dy, int dz, int log2s) {
     return (63 - __clzll(r2)) - 2 * (8 + log2s);
 }
 
-// table index of a far node (class c >= 6): direction cell of the offset in the ray set's
-// frame and the class, larger classes counting as the last
-__device__ __forceinline__ int alpha_key(int dx, int dy, int dz, int c, int orient, int log2m) {
-    c = c > kAlphaMax ? kAlphaMax : c;
+// table key of a far node (class c >= 6): direction cell of the offset in the ray set's
+// frame and the class, or -1 - cell when the class is served by the pixel table
+__device__ __forceinline__ int alpha_key(int dx, int dy, int dz, int c, int orient, int log2m, int c1) {
+    c = c > kAlphaMax ? kAlphaMax : c; // larger classes count as the last
     orient_offset(orient, dx, dy, dz);
-    return cube_cell(dx, dy, dz, log2m) * kAlphaClasses + (c - kAlphaFar);
+    const int cell = cube_cell(dx, dy, dz, log2m);
+    return c >= c1 ? -1 - cell : cell * (c1 - kAlphaFar) + (c - kAlphaFar);
 }
 
 // Segment of an accepted node in the pass [a, b) (Sec. 4.2): i = the largest radial point
@@ -365,11 +368,14 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
         const uint32_t k0 = (pk >> 6) & 63u, k1 = (pk >> 12) & 63u;
         if (k1 > k0) fbits = (k1 >= 32u ? 0xffffffffu : ((1u << k1) - 1u)) & ~((1u << k0) - 1u);
         const float4 qv = A.q[node];
-        int4 en = make_int4(0, 0, 0, 1);
+        auto lookup = [&](int cell) { return LDS_TABLE ? (int)tab8[cell] : (int)A.table[cell]; };
+        unsigned long long en = 1ull << 61; // no entry: the per-node kernel
+        int own = -1;                       // key served by the pixel table: the cell's pixel
         float vkh;
         int dx = 0, dy = 0, dz = 0;
         if (FAR && META) {
-            en = A.alpha[qkey[e]];
+            const int key = qkey[e];
+            if (key < 0) own = lookup(-1 - key); else en = A.alpha[key];
             beta = qbeta[e];
             vkh = qvk[e];
         } else {
@@ -379,7 +385,8 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             if (seg >= 0) beta = beta_of(dx, dy, dz, seg + pass_a);
             if (FAR) {
                 const int log2s = (31 - __clz(A.root_edge)) - (int)((pk >> 19) & 15u);
-                en = A.alpha[alpha_key(dx, dy, dz, dist_class(dx, dy, dz, log2s), orient, A.log2m)];
+                const int key = alpha_key(dx, dy, dz, dist_class(dx, dy, dz, log2s), orient, A.log2m, A.alpha_c1);
+                if (key < 0) own = lookup(-1 - key); else en = A.alpha[key];
             }
             orient_offset(orient, dx, dy, dz); // the angular kernel works in the ray set's frame
         }
@@ -395,14 +402,19 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             Lt = qv.x; LVk = qv.y; At = qv.z; Ak = qv.w;
             Vk = vkh;
         }
-        auto lookup = [&](int cell) { return LDS_TABLE ? (int)tab8[cell] : (int)A.table[cell]; };
-        if (FAR && en.w == 0) {
+        if (FAR && own >= 0) {
             tab = true;
-            pix[0] = en.x & 0xffff;
-            pix[1] = (int)((uint32_t)en.x >> 16);
-            pix[2] = en.y & 0xffff;
-            pix[3] = (int)((uint32_t)en.y >> 16);
-            counts = (uint32_t)en.z;
+            pix[0] = own;
+            counts = 64u;
+        } else if (FAR && !((en >> 61) & 1ull)) {
+            tab = true;
+            const uint32_t lo = (uint32_t)en, hi = (uint32_t)(en >> 32);
+            pix[0] = (int)(lo & 1023u);
+            pix[1] = (int)((lo >> 10) & 1023u);
+            pix[2] = (int)((lo >> 20) & 1023u);
+            pix[3] = (int)((lo >> 30) | ((hi & 255u) << 2));
+            const uint32_t c0 = (hi >> 8) & 127u, c1 = (hi >> 15) & 127u, c2 = (hi >> 22) & 127u;
+            counts = c0 | (c1 << 8) | (c2 << 16) | ((64u - c0 - c1 - c2) << 24);
         }
         if (FAR && META && !tab) {
             // a key that reaches more than 4 pixels: the per-node kernel needs the offset
@@ -654,7 +666,7 @@ __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const T
                 const int c = dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth);
                 far1 = !A.per_node && c >= kAlphaFar;
                 if (far1) {
-                    fkey = alpha_key(dx, dy, dz, c, T.orient, A.log2m);
+                    fkey = alpha_key(dx, dy, dz, c, T.orient, A.log2m, A.alpha_c1);
                     fbeta = h.content ? beta_of(dx, dy, dz, h.i) : 0.0f;
                     fvk = __int_as_float(pw);
                 }
@@ -822,7 +834,7 @@ __device__ void trace_target(const TraceArgs &A0, int ti, char *lds, const uint8
                                 const int c = dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth);
                                 far1 = !A.per_node && c >= kAlphaFar;
                                 if (far1) {
-                                    fkey = alpha_key(dx, dy, dz, c, orient, A.log2m);
+                                    fkey = alpha_key(dx, dy, dz, c, orient, A.log2m, A.alpha_c1);
                                     fbeta = h.content ? beta_of(dx, dy, dz, h.i) : 0.0f;
                                     fvk = __int_as_float(pw);
                                 }
@@ -1455,7 +1467,7 @@ int setup_instance(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, floa
     A = TraceArgs{};
     A.nodes = t->packed; A.q = t->q; A.pcol = t->pcol;
     A.targets = t->targets; A.leaf_cell = t->leaf_cell; A.cell_tau = t->cell_tau; A.cell_src = t->cell_src;
-    A.table = I.rt->table; A.alpha = I.rt->alpha; A.dirs = I.rt->dirs;
+    A.table = I.rt->table; A.alpha = I.rt->alpha; A.alpha_c1 = I.rt->alpha_c1; A.dirs = I.rt->dirs;
     A.per_node = p->per_node_kernel ? 1 : 0;
     A.work = ctx->d_ctl; A.err = ctx->d_ctl + 16;
     A.J = J; A.F = F; A.u_rad = u_rad; A.counters = counters;
@@ -1563,8 +1575,8 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     const int max_waves = max_waves_for(npix);
     // automatic choice: the one-block-per-target kernel when the one-wave kernel would need
     // a dozen passes or more (it re-walks the tree for each); below that the one-wave kernel
-    // is at least as fast on the MI355X (128^3 core, 11 passes: 1.96 s vs 1.98 s; AMR
-    // 256^3-equivalent, 15 passes: 2.77 s vs 2.64 s)
+    // is at least as fast on the MI355X (128^3 core, 7 passes: 1.67 s vs 1.71 s; AMR
+    // 256^3-equivalent, 15 passes: 2.60 s vs 2.34 s)
     const bool many_passes =
         tr_div_up(I.A.n_bins, choose_bp(I, p->bins_per_pass, lds_table, max_waves, count)) >= 12;
     if (!count && (p->kernel == 2 || (p->kernel == 0 && many_passes))) {

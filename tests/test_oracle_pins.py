@@ -461,6 +461,42 @@ def test_dust_root_is_unique_and_bracketed():
 # ----------------------------------------------------------------------------------
 # MLP guess network
 # ----------------------------------------------------------------------------------
+def test_mlp_linear_regime_is_a_matrix_product():
+    """With non-negative weights and inputs every pre-activation is positive, ReLU is the
+    identity and the network is the affine map W3 (W2 (W1 x + b1) + b2) + b3."""
+    H = 16
+    rng = np.random.default_rng(2)
+    W1, b1 = rng.uniform(0, 1, (H, 3)), rng.uniform(0.1, 1, H)
+    W2, b2 = rng.uniform(0, 1, (H, H)), rng.uniform(0.1, 1, H)
+    W3, b3 = rng.normal(size=H), rng.normal(size=1)
+    prm = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3, b3])
+    x = rng.uniform(0, 2, (50, 3))
+    _, out, _ = oracle.mlp(H, prm, x, np.zeros(50))
+    ref = (W3 @ (W2 @ (W1 @ x.T + b1[:, None]) + b2[:, None])).ravel() + b3[0]
+    assert np.allclose(out, ref, rtol=1e-12)
+
+
+def test_mlp_relu_cuts_negative_units():
+    """A hidden unit whose pre-activation is negative for every input contributes nothing:
+    changing its outgoing weight leaves the output unchanged, and its gradient is zero."""
+    H = 16
+    rng = np.random.default_rng(3)
+    npar = oracle.mlp_n_params(H)
+    prm = rng.normal(scale=0.4, size=npar)
+    x = rng.uniform(-1, 1, (40, 3))
+    y = rng.normal(size=40)
+    # unit 5 of the second layer: all incoming weights 0, bias -1
+    off_w2, off_b2, off_w3 = 4 * H, 4 * H + H * H, 5 * H + H * H
+    prm[off_w2 + 5 * H:off_w2 + 6 * H] = 0.0
+    prm[off_b2 + 5] = -1.0
+    l0, o0, g = oracle.mlp(H, prm, x, y)
+    p2 = prm.copy()
+    p2[off_w3 + 5] += 3.0
+    l1, o1, _ = oracle.mlp(H, p2, x, y)
+    assert np.array_equal(o0, o1)
+    assert g[off_w3 + 5] == 0.0 and g[off_b2 + 5] == 0.0
+
+
 def test_mlp_gradient_finite_differences():
     H = 16
     rng = np.random.default_rng(0)
