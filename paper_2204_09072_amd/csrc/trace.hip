@@ -675,25 +675,31 @@ __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const T
     }
 }
 
-// The arguments of a single-instance launch (the kernel's only argument) are read from the
-// kernel-argument segment where they are used (scalar loads), not held in scalar registers
-// across the persistent loop: there are more of them than registers, and the spilled
-// copies cost vector instructions to restore.  The empty asm hides the segment pointer's
-// value from the compiler so that the loads stay where they are.  Batched launches take
-// the instance's descriptor as given.
+// A trace kernel reads its instance's arguments where it uses them (scalar loads from the
+// constant address space), not held in scalar registers across the persistent loop: there
+// are more of them than registers, and the spilled copies cost vector instructions to
+// restore.  SRC says where they are: ARGS_KERNEL, the kernel's only argument, in the
+// kernel-argument segment; ARGS_BATCH, descriptor `inst` of the array whose address is
+// the first word of the kernel's argument.  The empty asm hides the segment pointer's value
+// from the compiler so that the loads stay where they are.
 typedef __attribute__((address_space(4))) const TraceArgs *KernArgs;
-template <bool KARG>
-__device__ __forceinline__ const TraceArgs &args_at(const TraceArgs &given) {
-    if (!KARG) return given;
-    KernArgs p = (KernArgs)__builtin_amdgcn_kernarg_segment_ptr();
-    asm volatile("" : "+s"(p));
-    return *(const TraceArgs *)p;
+enum { ARGS_KERNEL = 1, ARGS_BATCH = 2 };
+template <int SRC>
+__device__ __forceinline__ const TraceArgs &args_at(int inst) {
+    typedef __attribute__((address_space(4))) const KernArgs *KernArgsArray;
+    if (SRC == ARGS_KERNEL) {
+        KernArgs p = (KernArgs)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(p));
+        return *(const TraceArgs *)p;
+    }
+    KernArgsArray pp = (KernArgsArray)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(pp));
+    return *(const TraceArgs *)(*pp + __builtin_amdgcn_readfirstlane(inst));
 }
 
-template <int NSLOT, bool COUNT, bool LDS_TABLE, bool KARG = false>
-__device__ void trace_target(const TraceArgs &A0, int ti, char *lds, const uint8_t *tab8,
-                             float4 *thick) {
-    const TraceArgs &A = args_at<KARG>(A0);
+template <int NSLOT, bool COUNT, bool LDS_TABLE, int SRC>
+__device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, float4 *thick) {
+    const TraceArgs &A = args_at<SRC>(inst);
     const LdsLayout LL = lds_layout(A.npix, A.bp, A.kstack, COUNT);
     float *bins = reinterpret_cast<float *>(lds + LL.bins);
     uint32_t *flg = reinterpret_cast<uint32_t *>(lds + LL.flg);
@@ -720,7 +726,7 @@ __device__ void trace_target(const TraceArgs &A0, int ti, char *lds, const uint8
     int n_b = 0, n_h = 0, n_open = 0;
     const int n_pass = COUNT ? 1 : A.n_pass;
     for (int ps = 0; ps < n_pass; ++ps) {
-        const TraceArgs &A = args_at<KARG>(A0);
+        const TraceArgs &A = args_at<SRC>(inst);
         Pass P;
         P.a = 1 + ps * A.bp;
         P.b = P.a + A.bp;
@@ -737,7 +743,7 @@ __device__ void trace_target(const TraceArgs &A0, int ti, char *lds, const uint8
         int sp = 1, qf = 0, qs = 0; // stack depth, far and near queue lengths
         wave_sync();
         while (sp > 0 || qf > 0 || qs > 0) {
-            const TraceArgs &A = args_at<KARG>(A0);
+            const TraceArgs &A = args_at<SRC>(inst);
             if (sp > 0) {
                 const int npop = sp < 8 ? sp : 8;
                 const int r = lane >> 3, k = lane & 7;
@@ -1027,7 +1033,7 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
             t0 = __shfl(t0, 0) + lo;
             if (t0 >= hi) break;
             const int t1 = t0 + A.chunk < hi ? t0 + A.chunk : hi;
-            for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE, true>(A, ti, lds, tab8, thick);
+            for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE, ARGS_KERNEL>(0, ti, lds, tab8, thick);
         }
     }
 }
@@ -1063,9 +1069,9 @@ __host__ __device__ inline CoopLayout coop_layout(int npix, int bp, int fcap, in
     return L;
 }
 
-__device__ void coop_target(const TraceArgs &A0, int ti, char *lds, const CoopLayout &L, int fcap,
-                            const uint8_t *tab8, float4 *thick) {
-    const TraceArgs &A = args_at<true>(A0); // the kernel's only argument
+__device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, const uint8_t *tab8,
+                            float4 *thick) {
+    const TraceArgs &A = args_at<ARGS_KERNEL>(0);
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     float *bins = reinterpret_cast<float *>(lds + L.bins);
     uint32_t *flgm = reinterpret_cast<uint32_t *>(lds + L.flgm);
@@ -1118,7 +1124,7 @@ __device__ void coop_target(const TraceArgs &A0, int ti, char *lds, const CoopLa
             const uint32_t *Fc = (lev & 1) ? fr1 : fr0;
             uint32_t *Fn = (lev & 1) ? fr0 : fr1;
             for (;;) {
-                const TraceArgs &A = args_at<true>(A0);
+                const TraceArgs &A = args_at<ARGS_KERNEL>(0);
                 // 16 ranges per grab: every lane tests up to two nodes, one from each half
                 int c = 0;
                 if (lane == 0) c = atomicAdd(grab + lev, 16);
@@ -1314,7 +1320,7 @@ __global__ __launch_bounds__(1024) void k_trace_coop(TraceArgs A) {
             const int ti = *target + lo;
             __syncthreads();
             if (ti >= hi) break;
-            coop_target(A, ti, lds, L, fcap, tab8, thick);
+            coop_target(ti, lds, L, fcap, tab8, thick);
         }
     }
 }
@@ -1327,7 +1333,8 @@ __global__ __launch_bounds__(1024) void k_trace_coop(TraceArgs A) {
 constexpr int kMaxTabs = 4;
 
 struct BatchArgs {
-    const TraceArgs *__restrict__ inst; // [n_inst]
+    const TraceArgs *__restrict__ inst; // [n_inst]; the first member (read through the kernel
+                                        // argument segment's first word by the trace)
     const int *start;      // [n_inst + 1]
     int n_inst;
     int n_total;
@@ -1380,7 +1387,7 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace_batch(BatchArg
                 const int k = __builtin_amdgcn_readfirstlane(a);
                 const TraceArgs &A = B.inst[k];
                 const uint8_t *tab8 = reinterpret_cast<const uint8_t *>(smem) + B.tab_off[A.tab_slot];
-                trace_target<NSLOT, false, LDS_TABLE>(A, (ti - B.start[k]) * B.stride, lds, tab8, thick);
+                trace_target<NSLOT, false, LDS_TABLE, ARGS_BATCH>(k, (ti - B.start[k]) * B.stride, lds, tab8, thick);
             }
         }
     }
