@@ -743,7 +743,6 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
         int sp = 1, qf = 0, qs = 0; // stack depth, far and near queue lengths
         wave_sync();
         while (sp > 0 || qf > 0 || qs > 0) {
-            const TraceArgs &A = args_at<SRC>(inst);
             if (sp > 0) {
                 const int npop = sp < 8 ? sp : 8;
                 const int r = lane >> 3, k = lane & 7;
