@@ -231,7 +231,8 @@ int tr_mlp_create(tr_ctx *ctx, const float *params_host, const float *norm_host 
                   shift[3], scale[3], out_shift, out_scale */, tr_mlp **out);
 void tr_mlp_free(tr_mlp *mlp);
 int tr_mlp_get_params(tr_ctx *ctx, const tr_mlp *mlp, float *params_host);
-/* Forward only: x device float[n][3] (already normalised) -> y device float[n]. */
+/* Forward only: x device float[n][3] (already normalised) -> y device float[n]; n = 0 does
+ * nothing (x and y may then be NULL). */
 int tr_mlp_forward(tr_ctx *ctx, const tr_mlp *mlp, int64_t n, const float *x, float *y);
 /* Loss and gradients of the mean squared error for one batch: grad device
  * float[n_params] (overwritten), loss device float[1]. */

@@ -487,8 +487,9 @@ extern "C" int tr_mlp_get_params(tr_ctx *ctx, const tr_mlp *m, float *params) {
 
 extern "C" int tr_mlp_forward(tr_ctx *ctx, const tr_mlp *m, int64_t n, const float *x, float *y) {
     if (!ctx) return TR_EINVAL;
-    if (!m || !x || !y || n < 0) return tr_fail(ctx, TR_EINVAL, "tr_mlp_forward: bad argument");
+    if (!m || n < 0) return tr_fail(ctx, TR_EINVAL, "tr_mlp_forward: bad argument");
     if (n == 0) return TR_OK;
+    if (!x || !y) return tr_fail(ctx, TR_EINVAL, "tr_mlp_forward: null buffer");
     MlpArgs A = base_args(m, n);
     A.x = x; A.out = y;
     k_mlp_infer<FORWARD><<<grid_for(ctx, n, 3), 256, 0, ctx->stream>>>(A);

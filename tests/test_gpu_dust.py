@@ -99,3 +99,34 @@ def test_learned_guess_gain(lib, ctx):
         ctx.sync()
         say("  core %-10s mean iterations %.3f" % (name, float(it.float().mean().item())))
     mlp.free()
+
+
+@pytest.mark.parametrize("n", [0, 1, 33])
+def test_dust_and_network_tiny_inputs(lib, ctx, n):
+    """Empty and ragged inputs: nothing launched for n = 0; for a single state and for one
+    32-state step plus one, the solve against the oracle and the network's forward pass
+    against the oracle's bfloat16-rounded evaluation."""
+    import torch
+    from paper_2204_09072_amd.run import dust
+    s = W.dust_samples(max(n, 1), seed=40)[:n].astype(np.float32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    say("tiny inputs", n)
+    T, it = dust(ctx, d(s[:, 0]), d(s[:, 1]), d(s[:, 2]), W.SIGMA_SB, W.C_LIGHT)
+    H = lib.MLP_HIDDEN
+    prm = lib.init_mlp_params(5)
+    u = prm.view(np.uint32).astype(np.uint64)
+    prm = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32).view(np.float32)
+    m = lib.Mlp(ctx, prm)
+    x = np.random.default_rng(41).normal(size=(n, 3)).astype(np.float32)
+    xu = x.view(np.uint32).astype(np.uint64)
+    x = ((xu + 0x7FFF + ((xu >> 16) & 1)) & 0xFFFF0000).astype(np.uint32).view(np.float32).reshape(n, 3)
+    y = torch.zeros(n, device="cuda")
+    m.forward(d(x), y)
+    ctx.sync()
+    if n:
+        To, _ = oracle.dust_eq(s[:, 0].astype(np.float64), s[:, 1].astype(np.float64), s[:, 2].astype(np.float64),
+                               W.SIGMA_SB, W.C_LIGHT, 3.8e-33)
+        assert np.all(np.abs(T.cpu().numpy() - To) / To < 1e-5)
+        _, yo, _ = oracle.mlp(H, prm.astype(np.float64), x.astype(np.float64), np.zeros(n), round_bf16=True)
+        assert np.allclose(y.cpu().numpy(), yo, rtol=1e-2, atol=1e-2 * np.abs(yo).max())
+    m.free()

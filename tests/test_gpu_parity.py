@@ -186,6 +186,32 @@ def test_trace_parity_per_node_kernel(lib, ctx, case, kernel):
     _check_trace(J.cpu().numpy(), F.cpu().numpy().T, Jo, Fo)
 
 
+EDGE_CASES = {
+    # one 8^3 block: the smallest tree the builder accepts
+    "single_block": lambda: W.small_uniform(8, 1.0, 1.0, 1.0, n_side=1),
+    # every leaf optically thick (tau_b = 6.25): thick sums, merged runs carried across passes
+    "thick_box": lambda: W.small_uniform(16, 100.0, 1.0, 1.0, n_side=2),
+    # one thick blob in an empty box: zero content almost everywhere
+    "thick_blob": lambda: W.thick_blob(16, 2),
+    # dark absorbing medium lit by one star (Sec. 5.1 set-up)
+    "point_source": lambda: W.point_source_box(16, 0.5, n_side=2),
+}
+
+
+@pytest.mark.parametrize("case", list(EDGE_CASES))
+@pytest.mark.parametrize("kernel,bpp", [(1, 0), (1, 1), (2, 0)])
+def test_trace_parity_edge_cases(lib, ctx, case, kernel, bpp):
+    """Degenerate grids, every target against the oracle, both kernels (one radial point per
+    pass for the one-wave kernel as well: every merge run crosses passes)."""
+    from paper_2204_09072_amd.run import trace
+    w = EDGE_CASES[case]()
+    say("trace edge case", case, "kernel", kernel, "bins_per_pass", bpp)
+    tree, J, F, U = trace(ctx, w, kernel=kernel, bins_per_pass=bpp)
+    ctx.sync()
+    Jo, Fo = oracle.Tree(w).trace(oracle.params(w.n_side, theta=w.theta))
+    _check_trace(J.cpu().numpy(), F.cpu().numpy().T, Jo, Fo)
+
+
 def test_trace_parity_merge_off_and_background(lib, ctx):
     from paper_2204_09072_amd.run import trace
     w = TREE_CASES["amr_small"]()
