@@ -14,6 +14,8 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off",                      # fixed FP64 operation order in the tree build
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form",       # matrix-core results in VGPRs: no accumulator reads
+                                              # before the activations (guess network)
     "-Wno-unused-result", "-Wno-unused-value",
     "-I", os.path.join(ROOT, "include"), "-I", SRC,
 ]
