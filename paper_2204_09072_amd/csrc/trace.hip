@@ -1437,6 +1437,10 @@ constexpr int kLdsCu = 160 * 1024;
 
 int table_bytes(int M) { return (6 * M * M + 15) & ~15; }
 int max_waves_for(int npix) { return npix > 192 ? 4 : 16; } // the kernel's launch bound
+// waves a CU holds at once for the kernel's register use (the wide-ray kernel, ~190
+// VGPRs, two per SIMD); passes are sized so that this many waves share the CU's LDS
+// (wide rays, 128^3 core: 2 segments per pass and 8 waves 13.6 s, 4 and 4 waves 23.3 s)
+int waves_cu_for(int npix) { return npix > 192 ? 8 : 16; }
 int nslot_for(int npix) { return npix <= 64 ? 1 : (npix <= 192 ? 3 : 12); }
 // the one-wave kernels keep the pixel table in LDS for up to 64 rays (N_side <= 2, at most
 // 6 KB); beyond that only near nodes read it, from global memory, and the LDS holds more
@@ -1497,12 +1501,12 @@ int setup_instance(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, floa
 }
 
 // segments per pass of one instance under a requested value (0 = automatic: the longest
-// pass that lets max_waves waves share the CU's LDS next to `lds_table` bytes of tables)
-int choose_bp(const Inst &I, int want, int lds_table, int max_waves, bool count) {
+// pass that lets waves_cu waves share the CU's LDS next to `lds_table` bytes of tables)
+int choose_bp(const Inst &I, int want, int lds_table, int waves_cu, bool count) {
     int bp = want;
     if (bp <= 0) {
         bp = I.A.n_bins < kMaxBp ? I.A.n_bins : kMaxBp;
-        while (bp > 1 && lds_table + max_waves * lds_layout(I.npix, bp, I.A.kstack, count).total > kLdsCu) --bp;
+        while (bp > 1 && lds_table + waves_cu * lds_layout(I.npix, bp, I.A.kstack, count).total > kLdsCu) --bp;
     }
     if (bp > I.A.n_bins) bp = I.A.n_bins;
     if (bp > kMaxBp) bp = kMaxBp;
@@ -1581,17 +1585,17 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     const int max_waves = max_waves_for(npix);
     // automatic choice: the one-block-per-target kernel when the one-wave kernel would need
     // a dozen passes or more (it re-walks the tree for each); below that the one-wave kernel
-    // is at least as fast on the MI355X (128^3 core, 7 passes: 1.67 s vs 1.71 s; AMR
-    // 256^3-equivalent, 15 passes: 2.60 s vs 2.34 s)
+    // is at least as fast on the MI355X (128^3 core, 7 passes: 1.63 s vs 1.74 s; AMR
+    // 256^3-equivalent, 15 passes: 2.60 s vs 2.36 s)
     const bool many_passes =
-        tr_div_up(I.A.n_bins, choose_bp(I, p->bins_per_pass, lds_table, max_waves, count)) >= 12;
+        tr_div_up(I.A.n_bins, choose_bp(I, p->bins_per_pass, lds_table, waves_cu_for(npix), count)) >= 12;
     if (!count && (p->kernel == 2 || (p->kernel == 0 && many_passes))) {
         rc = launch_coop(ctx, I, p, npix <= 256 ? table_bytes(I.M) : 0);
         if (rc != TR_ENOTSUP) return rc;
         if (p->kernel == 2) return tr_fail(ctx, TR_EINVAL, "the one-block-per-target kernel does not fit this case");
         ctx->err.clear();
     }
-    set_bp(I, choose_bp(I, p->bins_per_pass, lds_table, max_waves, count), count);
+    set_bp(I, choose_bp(I, p->bins_per_pass, lds_table, waves_cu_for(npix), count), count);
     TraceArgs &A = I.A;
     A.chunk = p->chunk > 0 ? p->chunk : 4;
     A.lds_table = lds_table;
@@ -1670,7 +1674,7 @@ int batch_configure(tr_batch *b, Knobs k) {
     const int max_waves = max_waves_for(max_npix);
     int lds_wave = 16, thick_wave = 0;
     for (auto &I : b->inst) {
-        set_bp(I, choose_bp(I, k.bp, b->lds_table, max_waves, false), false);
+        set_bp(I, choose_bp(I, k.bp, b->lds_table, waves_cu_for(max_npix), false), false);
         lds_wave = I.A.lds_wave > lds_wave ? I.A.lds_wave : lds_wave;
         thick_wave = I.npix * (I.A.bp + 2) > thick_wave ? I.npix * (I.A.bp + 2) : thick_wave;
     }
