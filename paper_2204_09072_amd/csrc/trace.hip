@@ -14,13 +14,14 @@
 // Walk: a stack of child ranges (first child, count) in LDS; each step pops 8 ranges so
 // that the 64 lanes test 64 sibling nodes at once (one 16-byte record per node).  The
 // opening test, the pruning test and the radial bin search are exact integer
-// comparisons; the bin search takes a float estimate and falls back to 64-bit integers
-// only within rounding distance of a bin edge.  Accepted nodes that touch the pass are
-// compacted into one of two LDS queues and mapped 64 at a time, so the angular kernel runs
-// with every lane busy on the same code path: nodes at least 8 edges away take the
-// tabulated kernel (one direction cell and one table load per node), nearer ones the
-// per-node 8-point kernel.  A block holds several such waves; they share one copy of the
-// direction-cell table in LDS when the pixel ids fit a byte.
+// comparisons; the bin search compares r^2 with the pass's few radial points in 64-bit
+// integers (wide passes: a float estimate with a 64-bit fallback near a bin edge).
+// Accepted nodes that touch the pass are compacted into one of two LDS queues and mapped
+// 64 at a time, so the angular kernel runs with every lane busy on the same code path:
+// nodes at least 8 edges away take the tabulated kernel (the walk computes their table
+// key, one table load per node), nearer ones the per-node 8-point kernel.  A block holds
+// several such waves; with up to 64 rays they share one copy of the direction-cell table
+// in LDS, otherwise near nodes read it from global memory.
 #include "common.hpp"
 
 namespace {
@@ -339,14 +340,14 @@ __device__ __forceinline__ float beta_of(int dx, int dy, int dz, int i) {
 // depth << 19.
 //
 // Map queued nodes (Sec. 4.2.1/4.2.2): one lane per node, one LDS update per distinct pixel.
-// FAR: every node of the batch is at least 8 edges away and takes the tabulated kernel (one
-// direction cell, one table load); otherwise the per-node kernel: the node cube's 2x2x2
-// sub-points, each binned to a direction cell and its pixel, sorted to find the distinct
-// pixels.  SPLIT: merge flags in flg and thick-content flags in flgt, one bit per segment
-// of the pass each (passes of up to 31 segments); otherwise both in flg (thick bits from
-// bit 16).  META: far entries bring their table key, beta and V_thick from the walk, so
-// that the node's sums and its table entry are fetched side by side.
-template <bool LDS_TABLE, bool FAR, bool SPLIT = false, bool META = false>
+// FAR: every node of the batch is at least 8 edges away and takes the tabulated kernel; its
+// queue entry brings the table key, beta and V_thick from the walk, so that the node's sums
+// and its table entry are fetched side by side.  Otherwise the per-node kernel: the node
+// cube's 2x2x2 sub-points, each binned to a direction cell and its pixel, sorted to find
+// the distinct pixels.  SPLIT: merge flags in flg and thick-content flags in flgt, one bit
+// per segment of the pass each (passes of up to 31 segments); otherwise both in flg (thick
+// bits from bit 16).
+template <bool LDS_TABLE, bool FAR, bool SPLIT = false>
 __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *qnode, const uint32_t *qpk,
                                           int pass_a, int4 c256, int orient, const uint8_t *tab8, float *bins,
                                           uint32_t *flg, float4 *thick, uint32_t *flgt = nullptr,
@@ -373,7 +374,7 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
         int own = -1;                       // key served by the pixel table: the cell's pixel
         float vkh;
         int dx = 0, dy = 0, dz = 0;
-        if (FAR && META) {
+        if (FAR) {
             const int key = qkey[e];
             if (key < 0) own = lookup(-1 - key); else en = A.alpha[key];
             beta = qbeta[e];
@@ -383,11 +384,6 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             vkh = __int_as_float(p.w);
             dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
             if (seg >= 0) beta = beta_of(dx, dy, dz, seg + pass_a);
-            if (FAR) {
-                const int log2s = (31 - __clz(A.root_edge)) - (int)((pk >> 19) & 15u);
-                const int key = alpha_key(dx, dy, dz, dist_class(dx, dy, dz, log2s), orient, A.log2m, A.alpha_c1);
-                if (key < 0) own = lookup(-1 - key); else en = A.alpha[key];
-            }
             orient_offset(orient, dx, dy, dz); // the angular kernel works in the ray set's frame
         }
         if (leaf) {
@@ -416,7 +412,7 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             const uint32_t c0 = (hi >> 8) & 127u, c1 = (hi >> 15) & 127u, c2 = (hi >> 22) & 127u;
             counts = c0 | (c1 << 8) | (c2 << 16) | ((64u - c0 - c1 - c2) << 24);
         }
-        if (FAR && META && !tab) {
+        if (FAR && !tab) {
             // a key that reaches more than 4 pixels: the per-node kernel needs the offset
             const int4 p = A.pcol[node];
             dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
@@ -881,7 +877,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
             if (qf >= 64 || (sp == 0 && qf > 0)) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = lane < nq ? qf - nq + lane : -1;
-                map_queue<LDS_TABLE, true, false, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick,
+                map_queue<LDS_TABLE, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick,
                                                         nullptr, qkey, qbeta, qvk);
                 qf -= nq;
                 wave_sync();
@@ -1171,7 +1167,7 @@ __device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, co
                         wave_sync();
                         if (qf >= 64) {
                             const int e = qf - 64 + lane;
-                            map_queue<true, true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm,
+                            map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm,
                                                               thick, flgt, qkey, qbeta, qvk);
                             qf -= 64;
                             wave_sync();
@@ -1195,7 +1191,7 @@ __device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, co
             if (qf > 0) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = lane < nq ? qf - nq + lane : -1;
-                map_queue<true, true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt,
+                map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt,
                                                   qkey, qbeta, qvk);
                 qf -= nq;
                 wave_sync();
