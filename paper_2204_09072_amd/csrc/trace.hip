@@ -580,6 +580,7 @@ __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const T
                                            bool &enq, uint32_t &pk, bool &far1, int &fkey, float &fbeta,
                                            float &fvk) {
     const int4 nd = A.nodes[node];
+    const int4 pfc = A.pcol[node]; // fetched beside the walk record
     const int depth = (nd.x >> 16) & 15;
     const bool leaf = (nd.x >> 20) & 1;
     const bool thick = (nd.x >> 21) & 1;
@@ -650,9 +651,8 @@ __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const T
             if (leaf) {
                 dx = vx * TR_FX; dy = vy * TR_FX; dz = vz * TR_FX;
             } else {
-                const int4 p = A.pcol[node];
-                dx = p.x - T.c256.x; dy = p.y - T.c256.y; dz = p.z - T.c256.z;
-                pw = p.w;
+                dx = pfc.x - T.c256.x; dy = pfc.y - T.c256.y; dz = pfc.z - T.c256.z;
+                pw = pfc.w;
             }
             const SegHit h = seg_hit(dx, dy, dz, s, ext, G.a, G.b, G.last, A.n_bins);
             if (h.content || h.k1 > h.k0) {
@@ -752,6 +752,9 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                 float fbeta = 0.0f, fvk = 0.0f;
                 if (node >= 0) {
                     const int4 nd = A.nodes[node];
+                    // mapping position, needed by accepted h-nodes: fetched beside the walk
+                    // record rather than after the tests that depend on it
+                    const int4 pfc = A.pcol[node];
                     const int depth = (nd.x >> 16) & 15;
                     const bool leaf = (nd.x >> 20) & 1;
                     const bool thick = (nd.x >> 21) & 1;
@@ -822,9 +825,8 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                             if (leaf) {
                                 dx = vx * TR_FX; dy = vy * TR_FX; dz = vz * TR_FX;
                             } else {
-                                const int4 p = A.pcol[node];
-                                dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
-                                pw = p.w;
+                                dx = pfc.x - c256.x; dy = pfc.y - c256.y; dz = pfc.z - c256.z;
+                                pw = pfc.w;
                             }
                             const SegHit h = seg_hit(dx, dy, dz, s, ext, P.a, P.b, last, A.n_bins);
                             if (h.content || h.k1 > h.k0) {
