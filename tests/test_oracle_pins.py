@@ -641,3 +641,69 @@ def test_uv_rad_pressure_limits():
     a2, p2 = oracle.uv_rad_pressure(rho, x, 2 * N, u, 20 * 1.602e-12)
     assert np.allclose(p2[:, :2], 2 * p[:, :2], rtol=1e-14) and np.allclose(p2[:, 2], p[:, 2], rtol=1e-14)
     assert np.allclose(np.linalg.norm(a, axis=1), p.sum(axis=1) / rho, rtol=1e-14)
+
+
+# ----------------------------------------------------------------------------------
+# tabulated angular kernel (Sec. 4.2.1)
+# ----------------------------------------------------------------------------------
+def _cell_dirs(M):
+    """Unit centre direction of every direction cell (face f = 2 axis + sign, i and j
+    along the two other axes in increasing order)."""
+    out = np.zeros((6, M, M, 3))
+    c = (2 * np.arange(M) + 1 - M) / M
+    for f in range(6):
+        ax = f // 2
+        oa, ob = [a for a in range(3) if a != ax]
+        out[f, :, :, ax] = -1.0 if f & 1 else 1.0
+        out[f, :, :, oa] = c[:, None]
+        out[f, :, :, ob] = c[None, :]
+    return (out / np.linalg.norm(out, axis=-1, keepdims=True)).reshape(-1, 3)
+
+
+@pytest.mark.parametrize("ns", [1, 2, 4])
+def test_alpha_table_normalised_and_ordered(ns):
+    """Every entry shares its 64 sub-points out (alpha sums to one), lists distinct pixels
+    in ascending order with the unused slots last, and no key reaches more than 4 pixels."""
+    a = oracle.alpha_table(ns)
+    pix, cnt, flag = a[..., :4], a[..., 4:8], a[..., 8]
+    assert not flag.any()
+    assert np.all(cnt.sum(-1) == 64)
+    used = cnt > 0
+    assert np.all(used[..., 0])
+    assert np.all(used[..., :-1] >= used[..., 1:])            # used slots first
+    both = used[..., :-1] & used[..., 1:]
+    assert np.all(pix[..., 1:][both] > pix[..., :-1][both])   # strictly ascending
+    assert np.all((pix >= 0) & (pix < 12 * ns * ns))
+
+
+def test_alpha_table_points_along_its_direction():
+    """The count-weighted mean of the pixel centres of an entry points along its direction
+    cell: within one pixel radius for every key and class, and on average closer than the
+    cell's own pixel centre (a swapped axis or a flipped sign in the table's construction
+    would point it elsewhere)."""
+    ns = 4
+    a = oracle.alpha_table(ns)
+    dirs = oracle.ray_dirs(ns)
+    d = _cell_dirs(16 * ns)
+    m = np.einsum("kcs,kcsx->kcx", a[..., 4:8].astype(float), dirs[a[..., :4]]) / 64.0
+    m /= np.linalg.norm(m, axis=-1, keepdims=True)
+    ang = np.arccos(np.clip(np.einsum("kcx,kx->kc", m, d), -1, 1))
+    pixel_radius = np.sqrt(4 * np.pi / (12 * ns * ns))
+    assert ang.max() < pixel_radius
+    # sharing a node over the pixels its footprint covers brings the mean direction closer to
+    # the true one than the cell's own pixel centre alone
+    own = np.arccos(np.clip(np.einsum("kx,kx->k", dirs[oracle.cube_table(ns)], d), -1, 1))
+    assert ang.mean() < own.mean() < 0.5 * pixel_radius
+
+
+def test_alpha_table_narrows_with_distance():
+    """The sub-point cube shrinks with the distance class, so an entry reaches fewer pixels
+    on average as the class grows; in the last class every entry is the direction cell's
+    own pixel alone."""
+    ns = 4
+    a = oracle.alpha_table(ns)
+    npx = (a[..., 4:8] > 0).sum(-1).mean(0)
+    assert np.all(np.diff(npx) <= 1e-12)
+    own = oracle.cube_table(ns)
+    last = a[:, -1]
+    assert np.all(last[:, 4] == 64) and np.array_equal(last[:, 0], own)
