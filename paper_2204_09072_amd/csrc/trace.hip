@@ -31,7 +31,7 @@ constexpr float kPiF = 3.14159265358979f;
 // 0, the near-node one down from kQueue - 1; each holds < 64 entries before a walk step
 // adds at most 64
 constexpr int kQueue = 192;
-// far-node entries also carry their table key, radial kernel and V_thick (positions < 128)
+// far-node entries also carry their offset from the target (positions < 128)
 constexpr int kFarQ = 128;
 constexpr int kFields = 6;  // L_thin, A_thin, L_thick*V, A_thick, V_thick, Q
 constexpr int kThin = 2;    // fields held in LDS: L_thin, A_thin
@@ -337,12 +337,12 @@ __device__ __forceinline__ float beta_of(int dx, int dy, int dz, int i) {
 
 // Queue record of an accepted node: pk = content segment (i - a + 1, 0 = none) | first
 // merge flag << 6 | end of merge flags << 12 (both relative to the pass) | leaf << 18 |
-// depth << 19.
+// depth << 19 | thick content << 23.
 //
 // Map queued nodes (Sec. 4.2.1/4.2.2): one lane per node, one LDS update per distinct pixel.
 // FAR: every node of the batch is at least 8 edges away and takes the tabulated kernel; its
-// queue entry brings the table key, beta and V_thick from the walk, so that the node's sums
-// and its table entry are fetched side by side.  Otherwise the per-node kernel: the node
+// queue entry brings the node's offset from the walk, so the mapping position is not read
+// again and the node's sums and its table entry are fetched side by side.  Otherwise the per-node kernel: the node
 // cube's 2x2x2 sub-points, each binned to a direction cell and its pixel, sorted to find
 // the distinct pixels.  SPLIT: merge flags in flg and thick-content flags in flgt, one bit
 // per segment of the pass each (passes of up to 31 segments); otherwise both in flg (thick
@@ -351,8 +351,8 @@ template <bool LDS_TABLE, bool FAR, bool SPLIT = false>
 __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *qnode, const uint32_t *qpk,
                                           int pass_a, int4 c256, int orient, const uint8_t *tab8, float *bins,
                                           uint32_t *flg, float4 *thick, uint32_t *flgt = nullptr,
-                                          const int *qkey = nullptr, const float *qbeta = nullptr,
-                                          const float *qvk = nullptr) {
+                                          const int *qdx = nullptr, const int *qdy = nullptr,
+                                          const int *qdz = nullptr) {
     uint32_t starts = 0;
     int pix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     float Lt = 0, At = 0, LVk = 0, Ak = 0, Vk = 0, beta = 0;
@@ -375,10 +375,14 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
         float vkh;
         int dx = 0, dy = 0, dz = 0;
         if (FAR) {
-            const int key = qkey[e];
+            // the walk's offset: table key and radial kernel here, with every lane busy
+            dx = qdx[e]; dy = qdy[e]; dz = qdz[e];
+            const int log2s = (31 - __clz(A.root_edge)) - (int)((pk >> 19) & 15u);
+            if (seg >= 0) beta = beta_of(dx, dy, dz, seg + pass_a);
+            const int key = alpha_key(dx, dy, dz, dist_class(dx, dy, dz, log2s), orient, A.log2m, A.alpha_c1);
             if (key < 0) own = lookup(-1 - key); else en = A.alpha[key];
-            beta = qbeta[e];
-            vkh = qvk[e];
+            vkh = 0.0f;
+            if (!leaf && ((pk >> 23) & 1u)) vkh = __int_as_float(A.pcol[node].w); // thick h-node (rare)
         } else {
             const int4 p = A.pcol[node];
             vkh = __int_as_float(p.w);
@@ -412,12 +416,7 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             const uint32_t c0 = (hi >> 8) & 127u, c1 = (hi >> 15) & 127u, c2 = (hi >> 22) & 127u;
             counts = c0 | (c1 << 8) | (c2 << 16) | ((64u - c0 - c1 - c2) << 24);
         }
-        if (FAR && !tab) {
-            // a key that reaches more than 4 pixels: the per-node kernel needs the offset
-            const int4 p = A.pcol[node];
-            dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
-            orient_offset(orient, dx, dy, dz);
-        }
+        if (FAR && !tab) orient_offset(orient, dx, dy, dz); // more than 4 pixels: the per-node kernel
         if (!tab) {
             const int h = (TR_FX / 4) * s;
 #pragma unroll
@@ -577,8 +576,8 @@ struct PassGeo {
 template <bool COUNT>
 __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const Target &T, const PassGeo &G,
                                            int &n_b, int &n_h, int &n_open, bool &open, uint32_t &push,
-                                           bool &enq, uint32_t &pk, bool &far1, int &fkey, float &fbeta,
-                                           float &fvk) {
+                                           bool &enq, uint32_t &pk, bool &far1, int &fdx, int &fdy,
+                                           int &fdz) {
     const int4 nd = A.nodes[node];
     const int4 pfc = A.pcol[node]; // fetched beside the walk record
     const int depth = (nd.x >> 16) & 15;
@@ -647,25 +646,20 @@ __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const T
             maybe = rmax2 >= G.a4 && (G.last || rmin2 < G.b4);
         }
         if (maybe) {
-            int dx, dy, dz, pw = 0;
+            int dx, dy, dz;
             if (leaf) {
                 dx = vx * TR_FX; dy = vy * TR_FX; dz = vz * TR_FX;
             } else {
                 dx = pfc.x - T.c256.x; dy = pfc.y - T.c256.y; dz = pfc.z - T.c256.z;
-                pw = pfc.w;
             }
             const SegHit h = seg_hit(dx, dy, dz, s, ext, G.a, G.b, G.last, A.n_bins);
             if (h.content || h.k1 > h.k0) {
                 enq = true;
                 pk = (h.content ? (uint32_t)(h.i - G.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
-                     ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) | ((uint32_t)depth << 19);
-                const int c = dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth);
-                far1 = !A.per_node && c >= kAlphaFar;
-                if (far1) {
-                    fkey = alpha_key(dx, dy, dz, c, T.orient, A.log2m, A.alpha_c1);
-                    fbeta = h.content ? beta_of(dx, dy, dz, h.i) : 0.0f;
-                    fvk = __int_as_float(pw);
-                }
+                     ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) | ((uint32_t)depth << 19) |
+                     ((thick ? 1u : 0u) << 23);
+                far1 = !A.per_node && dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth) >= kAlphaFar;
+                fdx = dx; fdy = dy; fdz = dz;
             }
         }
     }
@@ -702,9 +696,8 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     uint32_t *stk = reinterpret_cast<uint32_t *>(lds + LL.stk);
     int *qnode = reinterpret_cast<int *>(lds + LL.qnode);
     uint32_t *qpk = reinterpret_cast<uint32_t *>(lds + LL.qpk);
-    int *qkey = reinterpret_cast<int *>(lds + LL.qmeta);
-    float *qbeta = reinterpret_cast<float *>(qkey + kFarQ);
-    float *qvk = qbeta + kFarQ;
+    int *qdx = reinterpret_cast<int *>(lds + LL.qmeta);
+    int *qdy = qdx + kFarQ, *qdz = qdy + kFarQ;
     const int lane = lane_id();
     const int tid = A.targets[ti];
     const int4 tr = A.nodes[tid];
@@ -748,8 +741,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                 const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
                 bool open = false, enq = false, far1 = false;
                 uint32_t push = 0, pk = 0;
-                int fkey = 0;
-                float fbeta = 0.0f, fvk = 0.0f;
+                int fdx = 0, fdy = 0, fdz = 0;
                 if (node >= 0) {
                     const int4 nd = A.nodes[node];
                     // mapping position, needed by accepted h-nodes: fetched beside the walk
@@ -821,26 +813,21 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                             maybe = rmax2 >= a4 && (last || rmin2 < b4);
                         }
                         if (maybe) {
-                            int dx, dy, dz, pw = 0;
+                            int dx, dy, dz;
                             if (leaf) {
                                 dx = vx * TR_FX; dy = vy * TR_FX; dz = vz * TR_FX;
                             } else {
                                 dx = pfc.x - c256.x; dy = pfc.y - c256.y; dz = pfc.z - c256.z;
-                                pw = pfc.w;
                             }
                             const SegHit h = seg_hit(dx, dy, dz, s, ext, P.a, P.b, last, A.n_bins);
                             if (h.content || h.k1 > h.k0) {
                                 enq = true;
                                 pk = (h.content ? (uint32_t)(h.i - P.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
                                      ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) |
-                                     ((uint32_t)depth << 19);
-                                const int c = dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth);
-                                far1 = !A.per_node && c >= kAlphaFar;
-                                if (far1) {
-                                    fkey = alpha_key(dx, dy, dz, c, orient, A.log2m, A.alpha_c1);
-                                    fbeta = h.content ? beta_of(dx, dy, dz, h.i) : 0.0f;
-                                    fvk = __int_as_float(pw);
-                                }
+                                     ((uint32_t)depth << 19) | ((thick ? 1u : 0u) << 23);
+                                far1 = !A.per_node &&
+                                       dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth) >= kAlphaFar;
+                                fdx = dx; fdy = dy; fdz = dz;
                             }
                         }
                     }
@@ -864,9 +851,9 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                         qnode[qp] = node;
                         qpk[qp] = pk;
                         if (far1) {
-                            qkey[qp] = fkey;
-                            qbeta[qp] = fbeta;
-                            qvk[qp] = fvk;
+                            qdx[qp] = fdx;
+                            qdy[qp] = fdy;
+                            qdz[qp] = fdz;
                         }
                     }
                     qf += __builtin_popcountll(fb);
@@ -880,7 +867,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = lane < nq ? qf - nq + lane : -1;
                 map_queue<LDS_TABLE, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick,
-                                                        nullptr, qkey, qbeta, qvk);
+                                                        nullptr, qdx, qdy, qdz);
                 qf -= nq;
                 wave_sync();
             }
@@ -1079,9 +1066,8 @@ __device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, co
     float *part = reinterpret_cast<float *>(lds + L.part);
     int *qnode = reinterpret_cast<int *>(lds + L.queues) + wv * 2 * kQueue;
     uint32_t *qpk = reinterpret_cast<uint32_t *>(qnode + kQueue);
-    int *qkey = reinterpret_cast<int *>(lds + L.qmeta) + wv * 3 * kFarQ;
-    float *qbeta = reinterpret_cast<float *>(qkey + kFarQ);
-    float *qvk = qbeta + kFarQ;
+    int *qdx = reinterpret_cast<int *>(lds + L.qmeta) + wv * 3 * kFarQ;
+    int *qdy = qdx + kFarQ, *qdz = qdy + kFarQ;
     const int tid = A.targets[ti];
     const int4 tr = A.nodes[tid];
     const int tx = tr.x & 0xffff, ty = tr.y & 0xffff, tz = tr.z;
@@ -1137,11 +1123,10 @@ __device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, co
                         const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
                         bool open = false, enq = false, far1 = false;
                         uint32_t push = 0, pk = 0;
-                        int fkey = 0;
-                        float fbeta = 0.0f, fvk = 0.0f;
+                        int fdx = 0, fdy = 0, fdz = 0;
                         if (node >= 0)
-                            visit_node<false>(A, node, T, G, n_b, n_h, n_open, open, push, enq, pk, far1, fkey, fbeta,
-                                              fvk);
+                            visit_node<false>(A, node, T, G, n_b, n_h, n_open, open, push, enq, pk, far1, fdx, fdy,
+                                              fdz);
                         const uint64_t bal = __ballot(open);
                         const int npush = __builtin_popcountll(bal);
                         if (npush) {
@@ -1159,9 +1144,9 @@ __device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, co
                             qnode[qp] = node;
                             qpk[qp] = pk;
                             if (far1) {
-                                qkey[qp] = fkey;
-                                qbeta[qp] = fbeta;
-                                qvk[qp] = fvk;
+                                qdx[qp] = fdx;
+                                qdy[qp] = fdy;
+                                qdz[qp] = fdz;
                             }
                         }
                         qf += __builtin_popcountll(fb);
@@ -1170,7 +1155,7 @@ __device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, co
                         if (qf >= 64) {
                             const int e = qf - 64 + lane;
                             map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm,
-                                                              thick, flgt, qkey, qbeta, qvk);
+                                                              thick, flgt, qdx, qdy, qdz);
                             qf -= 64;
                             wave_sync();
                         }
@@ -1194,7 +1179,7 @@ __device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, co
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = lane < nq ? qf - nq + lane : -1;
                 map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt,
-                                                  qkey, qbeta, qvk);
+                                                  qdx, qdy, qdz);
                 qf -= nq;
                 wave_sync();
             }
