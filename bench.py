@@ -238,6 +238,17 @@ def pmc_per_dispatch(paths):
     return res
 
 
+def trace_counters(paths):
+    """Counters of the trace launch (not the walk-count launch) from `rocprofv3 --pmc` runs of
+    --traffic-probe, one line per counter."""
+    rows = {}
+    for (k, _), v in pmc_per_dispatch(paths).items():
+        if "k_trace" in k and "<" in k and "true" not in k.split(",")[1]:
+            for c, x in v.items():
+                rows.setdefault(c, []).append(x)
+    return {c: float(np.mean(x)) for c, x in sorted(rows.items())}
+
+
 def write_traffic(workload, fetch_paths, write_paths, calib_bytes, out_paths):
     """HBM bytes per trace launch from FETCH_SIZE and WRITE_SIZE runs of --traffic-probe,
     each scaled by the same counter's reading for a plain copy of known size."""
@@ -359,6 +370,8 @@ def main():
                     help="one calibration copy and one trace launch, for rocprofv3 --pmc runs")
     ap.add_argument("--summarize", nargs="+", metavar="DIR",
                     help="print the per-kernel summary of rocprofv3 --kernel-trace --stats output")
+    ap.add_argument("--counters", nargs="+", metavar="DIR",
+                    help="print the trace launch's counters from rocprofv3 --pmc runs of --traffic-probe")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/trace_<workload>_traffic.json from two --pmc runs")
     ap.add_argument("--traffic-out", nargs="*", default=None)
@@ -367,6 +380,10 @@ def main():
     args = ap.parse_args()
     if args.summarize:
         print(summarize_kernels(args.summarize))
+        return
+    if args.counters:
+        for c, v in trace_counters(args.counters).items():
+            print(f"{c:24s} {v:.4e}")
         return
     if args.write_traffic:
         outs = args.traffic_out or [os.path.join(ROOT, "profiles", f"trace_{args.workload}_traffic.json")]
