@@ -12,7 +12,6 @@
 
 namespace {
 
-constexpr float kPiF = 3.14159265358979f;
 constexpr float kFloor = 2.7f;
 constexpr double kMH = 1.6735575e-24;
 

@@ -146,8 +146,8 @@ __device__ __forceinline__ int bin_below(int dx, int dy, int dz, int off, int nb
 // exact floor(num / den) for num < 2^31, den < 2^24, quotient < 2^8, from a float reciprocal
 __device__ __forceinline__ uint32_t exact_div(uint32_t num, uint32_t den, float rc) {
     uint32_t q = (uint32_t)((float)num * rc);
-    q -= __umul24(q, den) > num ? 1u : 0u;
-    q += __umul24(q + 1u, den) <= num ? 1u : 0u;
+    q -= (uint32_t)__umul24(q, den) > num ? 1u : 0u;
+    q += (uint32_t)__umul24(q + 1u, den) <= num ? 1u : 0u;
     return q;
 }
 
