@@ -795,8 +795,8 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                         // further s/2 for the merge flags.  R_i = i^2, so R_i <= r <=> i^4 <= r^2.
                         const int ext = thick && A.merge ? (s >> 1) : 0;
                         bool maybe;
+                        const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
                         if (leaf) {
-                            const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
                             if (ext == 0) {
                                 maybe = d2 >= a4 && (last || d2 < b4);
                             } else {
@@ -819,14 +819,28 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                             } else {
                                 dx = pfc.x - c256.x; dy = pfc.y - c256.y; dz = pfc.z - c256.z;
                             }
-                            const SegHit h = seg_hit(dx, dy, dz, s, ext, P.a, P.b, last, A.n_bins);
+                            SegHit h;
+                            int c;
+                            const int log2s = (31 - __clz(A.root_edge)) - depth;
+                            if (leaf && ext == 0 && P.b - P.a <= 4) {
+                                // a leaf sits on the lattice (r^2 = 2^16 d2): the pre-test above
+                                // was exact, and segment and class follow in 32 bits
+                                h.content = true;
+                                h.k0 = h.k1 = 0;
+                                int i = P.a;
+                                for (int k = P.a + 1; k < P.b; ++k) i += d2 >= (k * k) * (k * k) ? 1 : 0;
+                                h.i = i;
+                                c = (31 - __clz(d2)) - 2 * log2s;
+                            } else {
+                                h = seg_hit(dx, dy, dz, s, ext, P.a, P.b, last, A.n_bins);
+                                c = dist_class(dx, dy, dz, log2s);
+                            }
                             if (h.content || h.k1 > h.k0) {
                                 enq = true;
                                 pk = (h.content ? (uint32_t)(h.i - P.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
                                      ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) |
                                      ((uint32_t)depth << 19) | ((thick ? 1u : 0u) << 23);
-                                far1 = !A.per_node &&
-                                       dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth) >= kAlphaFar;
+                                far1 = !A.per_node && c >= kAlphaFar;
                                 fdx = dx; fdy = dy; fdz = dz;
                             }
                         }
