@@ -115,7 +115,8 @@ def train_interior(T, ctx, units, steps):
 
 DUST_VARIANTS = (("learned", True, {}), ("learned_linear_newton", True, dict(linear=True)),
                  ("plain", False, dict(start=1, linear=True, max_iter=250)),
-                 ("plain_log_newton", False, dict(start=1)), ("secant_log_newton", False, dict(start=0)))
+                 ("plain_log_newton", False, dict(start=1)), ("secant_log_newton", False, dict(start=0)),
+                 ("plain_bisection", False, dict(start=2, max_iter=250)))
 
 
 def dust_compare(T, ctx, mlp, rho, u_rad, t_gas, units, reps=20):
@@ -139,7 +140,8 @@ def dust_compare(T, ctx, mlp, rho, u_rad, t_gas, units, reps=20):
         ms_v = e0.elapsed_time(e1) / reps
         itf = it.float()
         stats[name] = {"ms": round(ms_v, 4), "solves_per_s": n / (ms_v / 1000.0),
-                       "mean_iters": round(float(itf.mean().item()), 3), "max_iters": int(it.max().item())}
+                       "mean_iters": round(float(itf.mean().item()), 3), "max_iters": int(it.max().item()),
+                       "iter_hist": [int(v) for v in torch.bincount(it.long()).cpu().numpy()]}
         sol[name] = out.cpu().numpy()
     ref = sol["plain"]
     for name in stats:
@@ -184,6 +186,12 @@ def cpu_baseline(w, n_pix, stride, u_rad=None, gpu_t_dust=None):
         if gpu_t_dust:
             errs = {k: float(np.max(np.abs(v[:m] - To) / To)) for k, v in gpu_t_dust.items()}
     t_step = t_tree + t_trace * (w.n_cells / len(cells)) + t_dust
+    # the same on one thread, over a sample 16 times sparser
+    cells1 = np.arange(0, w.n_cells, 16 * stride, dtype=np.int64)
+    t0 = time.perf_counter()
+    ot.trace(oracle.params(w.n_side, theta=w.theta), cells=cells1, n_threads=1)
+    t_trace1 = time.perf_counter() - t0
+    t_step1 = t_tree + t_trace1 * (w.n_cells / len(cells1)) + t_dust
     out = {
         "value": w.n_cells * n_pix / t_step,
         "unit": "target-ray evaluations/s",
@@ -194,6 +202,11 @@ def cpu_baseline(w, n_pix, stride, u_rad=None, gpu_t_dust=None):
                    f"{w.n_cells} targets, dust equilibrium timed on {min(w.n_cells, 200_000)} cells "
                    f"and scaled; estimated step {t_step:.1f} s"),
     }
+    out["single_thread"] = {
+        "value": w.n_cells * n_pix / t_step1, "cores": 1,
+        "sample": (f"ray tracing of every {16 * stride}th target ({len(cells1)} targets, {t_trace1:.2f} s) "
+                   f"on one thread, tree build and dust as above (the dust solve, {t_dust:.2f} s, on all threads); "
+                   f"estimated step {t_step1:.1f} s")}
     if errs:
         out["dust_max_rel_err"] = errs
     return out

@@ -197,8 +197,11 @@ typedef struct tr_dust_params {
     float rel_tol;    /* Newton stop |dT| <= rel_tol T (0 selects 1e-6) */
     int32_t max_iter; /* 0 selects 50 */
     int32_t start;    /* without a network: 0 = secant point of the bracket in (ln T, ln w),
-                         1 = the bracket end with the smaller |ln(w/K)| */
-    int32_t linear;   /* 0 = Newton on ln w(T) against ln T, 1 = Newton on the residual g(T) */
+                         1 = the bracket end with the smaller |ln(w/K)|, 2 = plain bisection
+                         of the bracket (no Newton steps; a reference for the iteration
+                         counts, stopping when the bracket width is <= rel_tol T) */
+    int32_t linear;   /* 0 = Newton on ln w(T) against ln T, 1 = Newton on the residual g(T);
+                         ignored by bisection */
 } tr_dust_params;
 
 /* rho, u_rad, t_gas: device float[n]; t_dust: device float[n]; iters: device uint8[n]

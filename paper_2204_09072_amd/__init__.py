@@ -340,8 +340,9 @@ def rad_force(ctx: Context, tree: Tree, F, a_rp, p_src=None):
 
 
 def dust_params(sigma, c, c_gd=3.8e-33, xi=1.0, rel_tol=0.0, max_iter=0, start=0, linear=False) -> DustParams:
-    """start 0: secant point of the bracket (log space); 1: the bracket end nearer the root.
-    linear: Newton on the residual itself instead of on ln w against ln T."""
+    """start 0: secant point of the bracket (log space); 1: the bracket end nearer the root;
+    2: plain bisection (no Newton steps).  linear: Newton on the residual itself instead of
+    on ln w against ln T."""
     return DustParams(float(sigma), float(c), float(c_gd), float(xi), float(rel_tol), int(max_iter),
                       int(start), int(bool(linear)))
 

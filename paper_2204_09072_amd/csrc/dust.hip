@@ -7,6 +7,7 @@
 // Newton's method (by default on ln w against ln T, see the kernel) runs inside that
 // bracket, with bisection when a step leaves it; the starting point is the bracket's secant
 // point in logarithms, the bracket end nearer the root, or the guess network's output.
+// Plain bisection of the same bracket is there as a reference for the step counts.
 #include "common.hpp"
 #include "mlp.hpp"
 
@@ -43,12 +44,13 @@ struct DustArgs {
     const float *guess; // learned starting points (START_LEARNED)
 };
 
-enum Start { START_SECANT = 0, START_END = 1, START_LEARNED = 2 };
+enum Start { START_SECANT = 0, START_END = 1, START_LEARNED = 2, START_BISECT = 3 };
 
 // START: where Newton begins (the bracket's secant point in logarithms, the bracket end
 // with the smaller |ln(w/K)|, or the guess network's output).  LOG: Newton on ln w against
 // ln T (else on g(T) itself).  Every variant keeps the bracket and bisects when a step
-// leaves it, and stops on the same rule.
+// leaves it, and stops on the same rule.  START_BISECT takes no Newton steps: the bracket
+// is halved until its width is within tol of its upper end, and T is its midpoint.
 template <int START, bool LOG>
 __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -86,6 +88,8 @@ __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
                 T = A.guess[c];
                 if (!(T > lo)) T = lo;   // also catches NaN from a poisoned network
                 if (!(T < hi)) T = hi;
+            } else if (START == START_BISECT) {
+                T = 0.5f * (lo + hi);
             } else {
                 const float wh = wf(hi, dw);
                 const float rl = __logf(K) - __logf(wl), rh = __logf(wh) - __logf(K);
@@ -101,6 +105,11 @@ __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
             for (it = 1; it <= A.max_iter; ++it) {
                 const float wv = wf(T, dw);
                 if (wv < K) lo = T; else hi = T;
+                if (START == START_BISECT) {
+                    T = 0.5f * (lo + hi);
+                    if (hi - lo <= A.tol * hi) break;
+                    continue;
+                }
                 float Tn = LOG ? T * __expf(-__logf(wv / K) * wv / (T * dw)) : T - (wv - K) / dw;
                 // a Newton step within tol: T is at the root to working precision.  Taken
                 // before the bracket test, since a step below FP32 resolution lands on the
@@ -131,7 +140,7 @@ extern "C" int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, con
         return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad argument");
     if (!(p->sigma > 0) || !(p->c > 0) || p->c_gd < 0 || p->xi <= 0)
         return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad constants");
-    if (p->start < 0 || p->start > 1 || p->linear < 0 || p->linear > 1)
+    if (p->start < 0 || p->start > 2 || p->linear < 0 || p->linear > 1)
         return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad start (%d) or linear (%d)", p->start, p->linear);
     if (n == 0) return TR_OK;
     TR_HIP(ctx, hipSetDevice(ctx->device));
@@ -160,6 +169,8 @@ extern "C" int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, con
         A.guess = ctx->ws_guess;
         if (p->linear) k_dust<START_LEARNED, false><<<blocks, 256, 0, ctx->stream>>>(A);
         else k_dust<START_LEARNED, true><<<blocks, 256, 0, ctx->stream>>>(A);
+    } else if (p->start == 2) {
+        k_dust<START_BISECT, true><<<blocks, 256, 0, ctx->stream>>>(A);
     } else if (p->start == 1) {
         if (p->linear) k_dust<START_END, false><<<blocks, 256, 0, ctx->stream>>>(A);
         else k_dust<START_END, true><<<blocks, 256, 0, ctx->stream>>>(A);

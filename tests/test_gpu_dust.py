@@ -28,7 +28,7 @@ def ctx(lib):
     c.close()
 
 
-@pytest.mark.parametrize("start,linear", [(0, False), (1, False), (0, True), (1, True)])
+@pytest.mark.parametrize("start,linear", [(0, False), (1, False), (0, True), (1, True), (2, False)])
 def test_dust_every_start_parity(lib, ctx, start, linear):
     import torch
     from paper_2204_09072_amd.run import dust
