@@ -395,8 +395,14 @@ def main():
         print(summarize_kernels(args.summarize))
         return
     if args.counters:
-        for c, v in trace_counters(args.counters).items():
+        cs = trace_counters(args.counters)
+        for c, v in cs.items():
             print(f"{c:24s} {v:.4e}")
+        if "TCC_HIT_sum" in cs and "TCC_MISS_sum" in cs:
+            print(f"L2 hit rate              {cs['TCC_HIT_sum'] / (cs['TCC_HIT_sum'] + cs['TCC_MISS_sum']):.4f}")
+        if "TCP_TOTAL_CACHE_ACCESSES_sum" in cs and "TCP_TCC_READ_REQ_sum" in cs:
+            print(f"L1 hit rate (reads)      "
+                  f"{1.0 - cs['TCP_TCC_READ_REQ_sum'] / cs['TCP_TOTAL_CACHE_ACCESSES_sum']:.4f}")
         return
     if args.write_traffic:
         outs = args.traffic_out or [os.path.join(ROOT, "profiles", f"trace_{args.workload}_traffic.json")]
