@@ -337,7 +337,7 @@ __device__ __forceinline__ float beta_of(int dx, int dy, int dz, int i) {
 
 // Queue record of an accepted node: pk = content segment (i - a + 1, 0 = none) | first
 // merge flag << 6 | end of merge flags << 12 (both relative to the pass) | leaf << 18 |
-// depth << 19 | thick content << 23.
+// depth << 19 | thick content << 23 | distance class << 24 (far nodes, at most kAlphaMax).
 //
 // Map queued nodes (Sec. 4.2.1/4.2.2): one lane per node, one LDS update per distinct pixel.
 // FAR: every node of the batch is at least 8 edges away and takes the tabulated kernel; its
@@ -377,9 +377,8 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
         if (FAR) {
             // the walk's offset: table key and radial kernel here, with every lane busy
             dx = qdx[e]; dy = qdy[e]; dz = qdz[e];
-            const int log2s = (31 - __clz(A.root_edge)) - (int)((pk >> 19) & 15u);
             if (seg >= 0) beta = beta_of(dx, dy, dz, seg + pass_a);
-            const int key = alpha_key(dx, dy, dz, dist_class(dx, dy, dz, log2s), orient, A.log2m, A.alpha_c1);
+            const int key = alpha_key(dx, dy, dz, (int)(pk >> 24), orient, A.log2m, A.alpha_c1);
             if (key < 0) own = lookup(-1 - key); else en = A.alpha[key];
             vkh = 0.0f;
             if (!leaf && ((pk >> 23) & 1u)) vkh = __int_as_float(A.pcol[node].w); // thick h-node (rare)
@@ -655,10 +654,11 @@ __device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const T
             const SegHit h = seg_hit(dx, dy, dz, s, ext, G.a, G.b, G.last, A.n_bins);
             if (h.content || h.k1 > h.k0) {
                 enq = true;
+                const int c = dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth);
+                far1 = !A.per_node && c >= kAlphaFar;
                 pk = (h.content ? (uint32_t)(h.i - G.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
                      ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) | ((uint32_t)depth << 19) |
-                     ((thick ? 1u : 0u) << 23);
-                far1 = !A.per_node && dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth) >= kAlphaFar;
+                     ((thick ? 1u : 0u) << 23) | (far1 ? (uint32_t)(c < kAlphaMax ? c : kAlphaMax) << 24 : 0u);
                 fdx = dx; fdy = dy; fdz = dz;
             }
         }
@@ -699,11 +699,13 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     int *qdx = reinterpret_cast<int *>(lds + LL.qmeta);
     int *qdy = qdx + kFarQ, *qdz = qdy + kFarQ;
     const int lane = lane_id();
-    const int tid = A.targets[ti];
+    // the target's values are the same on every lane: held in scalar registers
+    const int tid = __builtin_amdgcn_readfirstlane(A.targets[ti]);
     const int4 tr = A.nodes[tid];
-    const int tx = tr.x & 0xffff, ty = tr.y & 0xffff, tz = tr.z;
+    const int tx = __builtin_amdgcn_readfirstlane(tr.x & 0xffff), ty = __builtin_amdgcn_readfirstlane(tr.y & 0xffff),
+              tz = __builtin_amdgcn_readfirstlane(tr.z);
     const int4 c256 = make_int4(tx * TR_FX, ty * TR_FX, tz * TR_FX, 0);
-    const int orient = target_orient(A.orient, A.orient_seed, A.leaf_cell[tid]);
+    const int orient = __builtin_amdgcn_readfirstlane(target_orient(A.orient, A.orient_seed, A.leaf_cell[tid]));
     RayState<NSLOT> R;
 #pragma unroll
     for (int k = 0; k < NSLOT; ++k) {
@@ -837,10 +839,11 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                             }
                             if (h.content || h.k1 > h.k0) {
                                 enq = true;
+                                far1 = !A.per_node && c >= kAlphaFar;
                                 pk = (h.content ? (uint32_t)(h.i - P.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
                                      ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) |
-                                     ((uint32_t)depth << 19) | ((thick ? 1u : 0u) << 23);
-                                far1 = !A.per_node && c >= kAlphaFar;
+                                     ((uint32_t)depth << 19) | ((thick ? 1u : 0u) << 23) |
+                                     (far1 ? (uint32_t)(c < kAlphaMax ? c : kAlphaMax) << 24 : 0u);
                                 fdx = dx; fdy = dy; fdz = dz;
                             }
                         }
@@ -1028,7 +1031,7 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
         for (;;) {
             int t0 = 0;
             if (lane_id() == 0) t0 = atomicAdd(A.work + r, A.chunk);
-            t0 = __shfl(t0, 0) + lo;
+            t0 = __builtin_amdgcn_readfirstlane(t0) + lo;
             if (t0 >= hi) break;
             const int t1 = t0 + A.chunk < hi ? t0 + A.chunk : hi;
             for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE, ARGS_KERNEL>(0, ti, lds, tab8, thick);
