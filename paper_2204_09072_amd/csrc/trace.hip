@@ -328,6 +328,26 @@ __device__ __forceinline__ SegHit seg_hit(int dx, int dy, int dz, int s, int ext
     return h;
 }
 
+// Thresholds of a pass [a, b) of at most four radial points for the segment search, the
+// same on every lane: R_k^2 for k = a + 1 .. a + 3 in lattice units (k^4, leaves) and in
+// 1/256 lattice units (2^16 k^4, h-nodes, in FP64), each infinite from b on, and R_a^2,
+// R_b^2 in 1/256 units.  An offset below 2^19 per axis has r^2 < 2^40, so r^2, the
+// thresholds and their comparisons are exact in FP64, as in 64-bit integers.
+struct PassT {
+    int l1, l2, l3;
+    double ta, t1, t2, t3, tb;
+};
+__device__ __forceinline__ PassT pass_thresholds(int a, int b) {
+    auto l = [&](int k) { return k < b ? (k * k) * (k * k) : 0x7fffffff; };
+    auto t = [](int k) {
+        const double q = (double)(k * k);
+        return 65536.0 * (q * q);
+    };
+    const double inf = __builtin_inf();
+    return PassT{l(a + 1), l(a + 2), l(a + 3), t(a), a + 1 < b ? t(a + 1) : inf, a + 2 < b ? t(a + 2) : inf,
+                 a + 3 < b ? t(a + 3) : inf, t(b)};
+}
+
 // radial kernel beta = R_i^2 / r^2 of segment i (offsets in 1/256 lattice units)
 __device__ __forceinline__ float beta_of(int dx, int dy, int dz, int i) {
     const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
@@ -725,6 +745,8 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
         const int lo_cut = P.a * P.a, hi_cut = P.b * P.b;
         const int a4 = lo_cut * lo_cut, b4 = hi_cut * hi_cut; // R_a^2, R_b^2 in lattice units
         const bool last = P.b > A.n_bins;
+        const bool narrow = P.b - P.a <= 4;
+        const PassT PT = pass_thresholds(P.a, P.b);
         if (!COUNT) {
             const int nf = A.npix * A.bp * kThin;
             for (int k = lane; k < nf; k += 64) bins[k] = 0.0f;
@@ -824,15 +846,20 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                             SegHit h;
                             int c;
                             const int log2s = (31 - __clz(A.root_edge)) - depth;
-                            if (leaf && ext == 0 && P.b - P.a <= 4) {
+                            if (leaf && ext == 0 && narrow) {
                                 // a leaf sits on the lattice (r^2 = 2^16 d2): the pre-test above
                                 // was exact, and segment and class follow in 32 bits
                                 h.content = true;
                                 h.k0 = h.k1 = 0;
-                                int i = P.a;
-                                for (int k = P.a + 1; k < P.b; ++k) i += d2 >= (k * k) * (k * k) ? 1 : 0;
-                                h.i = i;
+                                h.i = P.a + (d2 >= PT.l1 ? 1 : 0) + (d2 >= PT.l2 ? 1 : 0) + (d2 >= PT.l3 ? 1 : 0);
                                 c = (31 - __clz(d2)) - 2 * log2s;
+                            } else if (ext == 0 && narrow) {
+                                // h-node: r^2 exact in FP64; the class is its binary exponent
+                                const double r2 = (double)dx * dx + (double)dy * dy + (double)dz * dz;
+                                h.content = r2 >= PT.ta && (last || r2 < PT.tb);
+                                h.k0 = h.k1 = 0;
+                                h.i = P.a + (r2 >= PT.t1 ? 1 : 0) + (r2 >= PT.t2 ? 1 : 0) + (r2 >= PT.t3 ? 1 : 0);
+                                c = (__builtin_amdgcn_frexp_exp(r2) - 1) - 2 * (8 + log2s);
                             } else {
                                 h = seg_hit(dx, dy, dz, s, ext, P.a, P.b, last, A.n_bins);
                                 c = dist_class(dx, dy, dz, log2s);
