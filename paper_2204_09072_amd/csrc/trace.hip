@@ -280,7 +280,7 @@ __device__ __forceinline__ int alpha_key(int dx, int dy, int dz, int c, int orie
     c = c > kAlphaMax ? kAlphaMax : c; // larger classes count as the last
     orient_offset(orient, dx, dy, dz);
     const int cell = cube_cell(dx, dy, dz, log2m);
-    return c >= c1 ? -1 - cell : cell * (c1 - kAlphaFar) + (c - kAlphaFar);
+    return c >= c1 ? -1 - cell : __mul24(cell, c1 - kAlphaFar) + (c - kAlphaFar);
 }
 
 // Segment of an accepted node in the pass [a, b) (Sec. 4.2): i = the largest radial point
@@ -329,29 +329,25 @@ __device__ __forceinline__ SegHit seg_hit(int dx, int dy, int dz, int s, int ext
 }
 
 // Thresholds of a pass [a, b) of at most four radial points for the segment search, the
-// same on every lane: R_k^2 for k = a + 1 .. a + 3 in lattice units (k^4, leaves) and in
-// 1/256 lattice units (2^16 k^4, h-nodes, in FP64), each infinite from b on, and R_a^2,
-// R_b^2 in 1/256 units.  An offset below 2^19 per axis has r^2 < 2^40, so r^2, the
+// same on every lane: R_k^2 = 2^16 k^4 in 1/256 lattice units, in FP64, for k = a, then
+// a + 1 .. a + 3 (each infinite from b on), and b.  An offset below 2^19 per axis has r^2 < 2^40, so r^2, the
 // thresholds and their comparisons are exact in FP64, as in 64-bit integers.
 struct PassT {
-    int l1, l2, l3;
     double ta, t1, t2, t3, tb;
 };
 __device__ __forceinline__ PassT pass_thresholds(int a, int b) {
-    auto l = [&](int k) { return k < b ? (k * k) * (k * k) : 0x7fffffff; };
     auto t = [](int k) {
         const double q = (double)(k * k);
         return 65536.0 * (q * q);
     };
     const double inf = __builtin_inf();
-    return PassT{l(a + 1), l(a + 2), l(a + 3), t(a), a + 1 < b ? t(a + 1) : inf, a + 2 < b ? t(a + 2) : inf,
-                 a + 3 < b ? t(a + 3) : inf, t(b)};
+    return PassT{t(a), a + 1 < b ? t(a + 1) : inf, a + 2 < b ? t(a + 2) : inf, a + 3 < b ? t(a + 3) : inf, t(b)};
 }
 
 // radial kernel beta = R_i^2 / r^2 of segment i (offsets in 1/256 lattice units)
 __device__ __forceinline__ float beta_of(int dx, int dy, int dz, int i) {
     const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-    const float R2 = (float)(TR_FX * i * i);
+    const float R2 = (float)(TR_FX * __mul24(i, i));
     return (R2 * R2) * rcp(fx * fx + fy * fy + fz * fz);
 }
 
@@ -763,117 +759,83 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                 sp -= npop;
                 wave_sync();
                 const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
-                bool open = false, enq = false, far1 = false;
-                uint32_t push = 0, pk = 0;
+                bool open, enq = false, far1 = false;
+                uint32_t push, pk = 0;
                 int fdx = 0, fdy = 0, fdz = 0;
-                if (node >= 0) {
-                    const int4 nd = A.nodes[node];
+                {
+                    // Every lane takes the same steps and selects by its node's kind instead
+                    // of branching (a lane without a node reads the root and keeps nothing).
+                    const bool valid = node >= 0;
+                    const int nid = valid ? node : 0;
+                    const int4 nd = A.nodes[nid];
                     // mapping position, needed by accepted h-nodes: fetched beside the walk
                     // record rather than after the tests that depend on it
-                    const int4 pfc = A.pcol[node];
+                    const int4 pfc = A.pcol[nid];
                     const int depth = (nd.x >> 16) & 15;
                     const bool leaf = (nd.x >> 20) & 1;
                     const bool thick = (nd.x >> 21) & 1;
                     const int s = A.root_edge >> depth;
                     const int vx = (nd.x & 0xffff) - tx, vy = (nd.y & 0xffff) - ty, vz = nd.z - tz;
-                    bool acc = false;
-                    if (leaf) {
-                        if (node != tid) {
-                            ++n_b;
-                            acc = true;
-                        }
-                    } else {
-                        // |v| < 2^12, s < 2^12: d2 and s^2 fit 24 bits
-                        const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
-                        const int s2 = __mul24(s, s);
-                        const bool accept = A.wide_open ? (int64_t)s2 * A.th_den2 < (int64_t)A.th_num2 * d2
-                                                        : s2 * A.th_den2 < A.th_num2 * d2;
-                        if (accept) {
-                            ++n_h;
-                            acc = true;
-                        } else {
-                            ++n_open;
-                            bool keep = true;
-                            if (!COUNT) {
-                                // keep a subtree when r_max + s/4 >= R_a and r_min - s/4 < R_b
-                                const int hs = s >> 1, q4 = s >> 2;
-                                const int ax = abs(vx), ay = abs(vy), az = abs(vz);
-                                const int nx = max(ax - hs, 0), ny = max(ay - hs, 0), nz = max(az - hs, 0);
-                                const int fx = ax + hs, fy = ay + hs, fz = az + hs;
-                                const int rmin2 = __mul24(nx, nx) + __mul24(ny, ny) + __mul24(nz, nz);
-                                const int rmax2 = __mul24(fx, fx) + __mul24(fy, fy) + __mul24(fz, fz);
-                                const int lo = lo_cut - q4, hi = hi_cut + q4;
-                                if (lo > 0 && rmax2 < __mul24(lo, lo)) keep = false;
-                                if (!last && rmin2 >= __mul24(hi, hi)) keep = false;
-                            }
-                            if (keep) {
-                                open = true;
-                                push = ((uint32_t)nd.w << 3) |
-                                       (uint32_t)(__builtin_popcount((nd.y >> 16) & 255) - 1);
-                            }
-                        }
+                    // |v| < 2^12, s < 2^12: d2 and s^2 fit 24 bits
+                    const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
+                    const int s2 = __mul24(s, s);
+                    const bool accept = A.wide_open ? (int64_t)s2 * A.th_den2 < (int64_t)A.th_num2 * d2
+                                                    : __umul24(s2, A.th_den2) < __umul24(A.th_num2, d2);
+                    const bool acc = valid && (leaf ? nid != tid : accept); // leaves always, but the target
+                    const bool opn = valid && !leaf && !accept;
+                    n_b += (valid && leaf && nid != tid) ? 1 : 0;
+                    n_h += (valid && !leaf && accept) ? 1 : 0;
+                    n_open += opn ? 1 : 0;
+                    const int ext = acc && thick && A.merge ? (s >> 1) : 0;
+                    // One box test serves both kinds of node (a lane is opened or accepted, not
+                    // both), in lattice units with R_i = i^2:
+                    //  - an opened h-node keeps its subtree when r_max + s/4 >= R_a and
+                    //    r_min - s/4 < R_b, with r over the node cube (half edge s/2);
+                    //  - an accepted node can reach the pass when r_max >= R_a and r_min < R_b:
+                    //    its mapping position lies in its cube (a leaf's is its centre, half
+                    //    edge 0), and thick material reaches a further s/2 for the merge flags.
+                    //    For a leaf with no extent the test is exact.
+                    const int he = opn ? (s >> 1) : (leaf ? 0 : (s >> 1)) + ext;
+                    const int ax = abs(vx), ay = abs(vy), az = abs(vz);
+                    const int nx = max(ax - he, 0), ny = max(ay - he, 0), nz = max(az - he, 0);
+                    const int fx = ax + he, fy = ay + he, fz = az + he;
+                    const int rmin2 = __mul24(nx, nx) + __mul24(ny, ny) + __mul24(nz, nz);
+                    const int rmax2 = __mul24(fx, fx) + __mul24(fy, fy) + __mul24(fz, fz);
+                    bool keep = true;
+                    if (!COUNT) {
+                        const int q4 = s >> 2;
+                        const int lo = lo_cut - q4, hi = hi_cut + q4;
+                        keep = !(lo > 0 && rmax2 < __mul24(lo, lo)) && (last || rmin2 < __mul24(hi, hi));
                     }
-                    if (!COUNT && acc) {
-                        // exact integer pre-test in lattice units: the mapping position lies in
-                        // the node cube, so r is within [r_min, r_max]; thick material reaches a
-                        // further s/2 for the merge flags.  R_i = i^2, so R_i <= r <=> i^4 <= r^2.
-                        const int ext = thick && A.merge ? (s >> 1) : 0;
-                        bool maybe;
-                        const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
-                        if (leaf) {
-                            if (ext == 0) {
-                                maybe = d2 >= a4 && (last || d2 < b4);
-                            } else {
-                                const int lo = P.a * P.a - ext, hi = P.b * P.b + ext;
-                                maybe = (lo <= 0 || d2 >= __mul24(lo, lo)) && (last || d2 < __mul24(hi, hi));
-                            }
+                    open = opn && keep;
+                    push = ((uint32_t)nd.w << 3) | (uint32_t)(__builtin_popcount((nd.y >> 16) & 255) - 1);
+                    if (!COUNT) {
+                        const bool maybe = acc && rmax2 >= a4 && (last || rmin2 < b4);
+                        const int dx = leaf ? vx * TR_FX : pfc.x - c256.x;
+                        const int dy = leaf ? vy * TR_FX : pfc.y - c256.y;
+                        const int dz = leaf ? vz * TR_FX : pfc.z - c256.z;
+                        const int log2s = (31 - __clz(A.root_edge)) - depth;
+                        SegHit h;
+                        int c;
+                        if (ext == 0 && narrow) {
+                            // r^2 exact in FP64 (a leaf's is 2^16 d2); the class is its binary
+                            // exponent
+                            const double r2 = (double)dx * dx + (double)dy * dy + (double)dz * dz;
+                            h.content = r2 >= PT.ta && (last || r2 < PT.tb);
+                            h.k0 = h.k1 = 0;
+                            h.i = P.a + (r2 >= PT.t1 ? 1 : 0) + (r2 >= PT.t2 ? 1 : 0) + (r2 >= PT.t3 ? 1 : 0);
+                            c = (__builtin_amdgcn_frexp_exp(r2) - 1) - 2 * (8 + log2s);
                         } else {
-                            const int hs = (s >> 1) + ext;
-                            const int ax = abs(vx), ay = abs(vy), az = abs(vz);
-                            const int nx = max(ax - hs, 0), ny = max(ay - hs, 0), nz = max(az - hs, 0);
-                            const int fx = ax + hs, fy = ay + hs, fz = az + hs;
-                            const int rmin2 = __mul24(nx, nx) + __mul24(ny, ny) + __mul24(nz, nz);
-                            const int rmax2 = __mul24(fx, fx) + __mul24(fy, fy) + __mul24(fz, fz);
-                            maybe = rmax2 >= a4 && (last || rmin2 < b4);
+                            h = seg_hit(dx, dy, dz, s, ext, P.a, P.b, last, A.n_bins);
+                            c = dist_class(dx, dy, dz, log2s);
                         }
-                        if (maybe) {
-                            int dx, dy, dz;
-                            if (leaf) {
-                                dx = vx * TR_FX; dy = vy * TR_FX; dz = vz * TR_FX;
-                            } else {
-                                dx = pfc.x - c256.x; dy = pfc.y - c256.y; dz = pfc.z - c256.z;
-                            }
-                            SegHit h;
-                            int c;
-                            const int log2s = (31 - __clz(A.root_edge)) - depth;
-                            if (leaf && ext == 0 && narrow) {
-                                // a leaf sits on the lattice (r^2 = 2^16 d2): the pre-test above
-                                // was exact, and segment and class follow in 32 bits
-                                h.content = true;
-                                h.k0 = h.k1 = 0;
-                                h.i = P.a + (d2 >= PT.l1 ? 1 : 0) + (d2 >= PT.l2 ? 1 : 0) + (d2 >= PT.l3 ? 1 : 0);
-                                c = (31 - __clz(d2)) - 2 * log2s;
-                            } else if (ext == 0 && narrow) {
-                                // h-node: r^2 exact in FP64; the class is its binary exponent
-                                const double r2 = (double)dx * dx + (double)dy * dy + (double)dz * dz;
-                                h.content = r2 >= PT.ta && (last || r2 < PT.tb);
-                                h.k0 = h.k1 = 0;
-                                h.i = P.a + (r2 >= PT.t1 ? 1 : 0) + (r2 >= PT.t2 ? 1 : 0) + (r2 >= PT.t3 ? 1 : 0);
-                                c = (__builtin_amdgcn_frexp_exp(r2) - 1) - 2 * (8 + log2s);
-                            } else {
-                                h = seg_hit(dx, dy, dz, s, ext, P.a, P.b, last, A.n_bins);
-                                c = dist_class(dx, dy, dz, log2s);
-                            }
-                            if (h.content || h.k1 > h.k0) {
-                                enq = true;
-                                far1 = !A.per_node && c >= kAlphaFar;
-                                pk = (h.content ? (uint32_t)(h.i - P.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
-                                     ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) |
-                                     ((uint32_t)depth << 19) | ((thick ? 1u : 0u) << 23) |
-                                     (far1 ? (uint32_t)(c < kAlphaMax ? c : kAlphaMax) << 24 : 0u);
-                                fdx = dx; fdy = dy; fdz = dz;
-                            }
-                        }
+                        enq = maybe && (h.content || h.k1 > h.k0);
+                        far1 = enq && !A.per_node && c >= kAlphaFar;
+                        pk = (h.content ? (uint32_t)(h.i - P.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
+                             ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) | ((uint32_t)depth << 19) |
+                             ((thick ? 1u : 0u) << 23) |
+                             (far1 ? (uint32_t)(c < kAlphaMax ? c : kAlphaMax) << 24 : 0u);
+                        fdx = dx; fdy = dy; fdz = dz;
                     }
                 }
                 const uint64_t below = (1ull << lane) - 1ull;
@@ -1512,9 +1474,11 @@ int setup_instance(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, floa
     A.npix = I.npix; A.log2m = log2m; A.n_bins = t->n_bins;
     A.merge = p->merge ? 1 : 0;
     A.th_num2 = (int)(num * num); A.th_den2 = (int)(den * den);
-    // 32-bit products are exact when num^2 d^2 and den^2 s^2 stay below 2^31
+    // 32-bit products are exact when num^2 d^2 and den^2 s^2 stay below 2^31, and take the
+    // 24-bit multiplier when every factor is below 2^24 (d^2 < 3 * 2048^2 always is)
     const int64_t max_d2 = 3 * t->root_edge * t->root_edge, max_s2 = t->root_edge * t->root_edge;
-    A.wide_open = (num * num * max_d2 >= ((int64_t)1 << 31) || den * den * max_s2 >= ((int64_t)1 << 31)) ? 1 : 0;
+    A.wide_open = (num * num * max_d2 >= ((int64_t)1 << 31) || den * den * max_s2 >= ((int64_t)1 << 31) ||
+                   num * num >= ((int64_t)1 << 24) || den * den >= ((int64_t)1 << 24)) ? 1 : 0;
     A.omega = (float)(4.0 * 3.14159265358979323846 / I.npix);
     A.j_bg = p->j_bg;
     A.c_light = (float)t->c_light;
