@@ -364,7 +364,7 @@ __device__ __forceinline__ float beta_of(int dx, int dy, int dz, int i) {
 // per segment of the pass each (passes of up to 31 segments); otherwise both in flg (thick
 // bits from bit 16).
 template <bool LDS_TABLE, bool FAR, bool SPLIT = false>
-__device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *qnode, const uint32_t *qpk,
+__device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid, const int *qnode, const uint32_t *qpk,
                                           int pass_a, int4 c256, int orient, const uint8_t *tab8, float *bins,
                                           uint32_t *flg, float4 *thick, uint32_t *flgt = nullptr,
                                           const int *qdx = nullptr, const int *qdy = nullptr,
@@ -376,14 +376,18 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
     uint32_t fbits = 0;
     uint32_t counts = 0; // tabulated entries: counts out of 64 of pix[0..3]
     bool tab = false;
-    if (e >= 0) {
-        const int node = qnode[e];
-        const uint32_t pk = qpk[e];
+    {
+        // Every lane reads a queue entry (e is in range on every lane); a lane without one of
+        // its own (!valid, only at the end of a pass) repeats another lane's and carries no
+        // counts, segment or flags, so the lanes take the same steps without branching.
+        const int ev = e;
+        const int node = qnode[ev];
+        const uint32_t pk = qpk[ev];
         const bool leaf = (pk >> 18) & 1u;
         const int s = A.root_edge >> ((pk >> 19) & 15u);
-        seg = (int)(pk & 63u) - 1;
+        seg = valid ? (int)(pk & 63u) - 1 : -1;
         const uint32_t k0 = (pk >> 6) & 63u, k1 = (pk >> 12) & 63u;
-        if (k1 > k0) fbits = (k1 >= 32u ? 0xffffffffu : ((1u << k1) - 1u)) & ~((1u << k0) - 1u);
+        fbits = valid && k1 > k0 ? (k1 >= 32u ? 0xffffffffu : ((1u << k1) - 1u)) & ~((1u << k0) - 1u) : 0u;
         const float4 qv = A.q[node];
         auto lookup = [&](int cell) { return LDS_TABLE ? (int)tab8[cell] : (int)A.table[cell]; };
         unsigned long long en = 1ull << 61; // no entry: the per-node kernel
@@ -392,17 +396,21 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
         int dx = 0, dy = 0, dz = 0;
         if (FAR) {
             // the walk's offset: table key and radial kernel here, with every lane busy
-            dx = qdx[e]; dy = qdy[e]; dz = qdz[e];
-            if (seg >= 0) beta = beta_of(dx, dy, dz, seg + pass_a);
+            dx = qdx[ev]; dy = qdy[ev]; dz = qdz[ev];
+            beta = beta_of(dx, dy, dz, (seg > 0 ? seg : 0) + pass_a);
             const int key = alpha_key(dx, dy, dz, (int)(pk >> 24), orient, A.log2m, A.alpha_c1);
-            if (key < 0) own = lookup(-1 - key); else en = A.alpha[key];
+            // both reads, the one not needed at a harmless index, instead of a branch
+            const unsigned long long ek = A.alpha[key < 0 ? 0 : key];
+            const int ok = lookup(key < 0 ? -1 - key : 0);
+            en = key < 0 ? 0ull : ek;
+            own = key < 0 ? ok : -1;
             vkh = 0.0f;
             if (!leaf && ((pk >> 23) & 1u)) vkh = __int_as_float(A.pcol[node].w); // thick h-node (rare)
         } else {
             const int4 p = A.pcol[node];
             vkh = __int_as_float(p.w);
             dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
-            if (seg >= 0) beta = beta_of(dx, dy, dz, seg + pass_a);
+            beta = beta_of(dx, dy, dz, (seg > 0 ? seg : 0) + pass_a);
             orient_offset(orient, dx, dy, dz); // the angular kernel works in the ray set's frame
         }
         if (leaf) {
@@ -417,19 +425,16 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             Lt = qv.x; LVk = qv.y; At = qv.z; Ak = qv.w;
             Vk = vkh;
         }
-        if (FAR && own >= 0) {
-            tab = true;
-            pix[0] = own;
-            counts = 64u;
-        } else if (FAR && !((en >> 61) & 1ull)) {
-            tab = true;
+        if (FAR) {
+            // the cell's own pixel (all 64 sub-points), or up to 4 tabulated pixels and counts
             const uint32_t lo = (uint32_t)en, hi = (uint32_t)(en >> 32);
-            pix[0] = (int)(lo & 1023u);
+            const uint32_t c0 = (hi >> 8) & 127u, c1 = (hi >> 15) & 127u, c2 = (hi >> 22) & 127u;
+            tab = own >= 0 || !((en >> 61) & 1ull);
+            pix[0] = own >= 0 ? own : (int)(lo & 1023u);
             pix[1] = (int)((lo >> 10) & 1023u);
             pix[2] = (int)((lo >> 20) & 1023u);
             pix[3] = (int)((lo >> 30) | ((hi & 255u) << 2));
-            const uint32_t c0 = (hi >> 8) & 127u, c1 = (hi >> 15) & 127u, c2 = (hi >> 22) & 127u;
-            counts = c0 | (c1 << 8) | (c2 << 16) | ((64u - c0 - c1 - c2) << 24);
+            counts = !valid ? 0u : own >= 0 ? 64u : c0 | (c1 << 8) | (c2 << 16) | ((64u - c0 - c1 - c2) << 24);
         }
         if (FAR && !tab) orient_offset(orient, dx, dy, dz); // more than 4 pixels: the per-node kernel
         if (!tab) {
@@ -446,9 +451,9 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
             cswap(pix[2], pix[4]); cswap(pix[3], pix[5]);
             cswap(pix[1], pix[4]); cswap(pix[3], pix[6]);
             cswap(pix[1], pix[2]); cswap(pix[3], pix[4]); cswap(pix[5], pix[6]);
-            starts = 1u;
+            starts = valid ? 1u : 0u;
 #pragma unroll
-            for (int k = 1; k < 8; ++k) starts |= (pix[k] != pix[k - 1] ? 1u : 0u) << k;
+            for (int k = 1; k < 8; ++k) starts |= (valid && pix[k] != pix[k - 1] ? 1u : 0u) << k;
         }
     }
     // One update per (node, pixel); each loop runs as often as the busiest lane needs.  Thin
@@ -456,26 +461,28 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
     // (pixel, segment) -- siblings of one parent usually do -- so that one LDS atomic per
     // run, not per lane, reaches the bins.
     const int lane = lane_id(), rl = lane & 15;
-    auto update = [&](int px, float al, float ab, int &key, float &v0, float &v1) {
-        uint32_t fl = fbits, ft = 0u;
-        if (seg >= 0) {
-            key = px * A.bp + seg;
-            v0 = ab * Lt;
-            v1 = ab * At;
-            if (Vk > 0.0f) {
-                float *tk = reinterpret_cast<float *>(thick + px * A.bp + seg);
-                atomicAdd(tk + 0, al * LVk);
-                atomicAdd(tk + 1, al * Ak);
-                atomicAdd(tk + 2, al * Vk);
-                atomicAdd(tk + 3, ab * Vk);
-                ft = 1u << seg;
-            }
+    // on: the lane has this pixel; thin content goes out through key/v0/v1 (key -1: none),
+    // thick content and merge flags (both rare) straight to their accumulators
+    auto update = [&](bool on, int px, float al, float ab, int &key, float &v0, float &v1) {
+        const bool cs = on && seg >= 0;
+        key = cs ? px * A.bp + seg : -1;
+        v0 = cs ? ab * Lt : 0.0f;
+        v1 = cs ? ab * At : 0.0f;
+        uint32_t ft = 0u;
+        if (cs && Vk > 0.0f) {
+            float *tk = reinterpret_cast<float *>(thick + px * A.bp + seg);
+            atomicAdd(tk + 0, al * LVk);
+            atomicAdd(tk + 1, al * Ak);
+            atomicAdd(tk + 2, al * Vk);
+            atomicAdd(tk + 3, ab * Vk);
+            ft = 1u << seg;
         }
+        const uint32_t fm = on ? fbits : 0u;
         if (SPLIT) {
-            if (fl) atomicOr(flg + px, fl);
+            if (fm) atomicOr(flg + px, fm);
             if (ft) atomicOr(flgt + px, ft);
         } else {
-            fl |= ft << 16;
+            const uint32_t fl = fm | (ft << 16);
             if (fl) atomicOr(flg + px, fl);
         }
     };
@@ -491,10 +498,10 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
         seg_sum_step<4>(rl, rid, v0, v1);
         seg_sum_step<8>(rl, rid, v0, v1);
         const int nrid = dpp_shl<1>(rid, 0);
-        if (key >= 0 && (rl == 15 || nrid != rid)) {
+        if (key >= 0 && (rl == 15 || nrid != rid) && (v0 != 0.0f || v1 != 0.0f)) {
             float *bb = bins + key * kThin;
-            if (v0 != 0.0f) atomicAdd(bb + 0, v0);
-            if (v1 != 0.0f) atomicAdd(bb + 1, v1);
+            atomicAdd(bb + 0, v0);
+            atomicAdd(bb + 1, v1);
         }
     };
     if (FAR) {
@@ -505,35 +512,32 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, const int *
         for (int t = 0; t < 4; ++t) {
             const uint32_t ct = tab ? (counts >> (8 * t)) & 255u : 0u;
             if (!__ballot(ct != 0u)) break;
-            int key = -1;
-            float v0 = 0.0f, v1 = 0.0f;
-            if (ct) {
-                const float al = (1.0f / 64.0f) * (float)ct;
-                update(pix[t], al, al * beta, key, v0, v1);
-            }
+            int key;
+            float v0, v1;
+            const float al = (1.0f / 64.0f) * (float)ct;
+            update(ct != 0u, pix[t], al, al * beta, key, v0, v1);
             if (t == 0) {
                 flush(key, v0, v1);
-            } else if (key >= 0) {
+            } else if (key >= 0 && (v0 != 0.0f || v1 != 0.0f)) {
                 float *bb = bins + key * kThin;
-                if (v0 != 0.0f) atomicAdd(bb + 0, v0);
-                if (v1 != 0.0f) atomicAdd(bb + 1, v1);
+                atomicAdd(bb + 0, v0);
+                atomicAdd(bb + 1, v1);
             }
         }
     }
     // per-node kernel: runs of equal pixels among the 8 sorted sub-point pixels
     while (__ballot(starts != 0u)) {
-        int key = -1;
-        float v0 = 0.0f, v1 = 0.0f;
-        if (starts) {
-            const int k = __builtin_ctz(starts);
-            starts &= starts - 1u;
-            int px = pix[0];
+        int key;
+        float v0, v1;
+        const bool on = starts != 0u;
+        const int k = on ? __builtin_ctz(starts) : 0;
+        starts &= starts - 1u;
+        int px = pix[0];
 #pragma unroll
-            for (int j = 1; j < 8; ++j) px = k == j ? pix[j] : px;
-            const int kn = starts ? __builtin_ctz(starts) : 8;
-            const float al = 0.125f * (float)(kn - k);
-            update(px, al, al * beta, key, v0, v1);
-        }
+        for (int j = 1; j < 8; ++j) px = k == j ? pix[j] : px;
+        const int kn = starts ? __builtin_ctz(starts) : 8;
+        const float al = 0.125f * (float)(kn - k);
+        update(on, px, al, al * beta, key, v0, v1);
         flush(key, v0, v1);
     }
 }
@@ -871,16 +875,16 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
             // map full batches, or whatever is left once the walk of the pass is done
             if (qf >= 64 || (sp == 0 && qf > 0)) {
                 const int nq = qf >= 64 ? 64 : qf;
-                const int e = lane < nq ? qf - nq + lane : -1;
-                map_queue<LDS_TABLE, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick,
+                const int e = qf - nq + (lane < nq ? lane : 0);
+                map_queue<LDS_TABLE, true>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick,
                                                         nullptr, qdx, qdy, qdz);
                 qf -= nq;
                 wave_sync();
             }
             if (qs >= 64 || (sp == 0 && qs > 0)) {
                 const int nq = qs >= 64 ? 64 : qs;
-                const int e = lane < nq ? kQueue - qs + lane : -1;
-                map_queue<LDS_TABLE, false>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick);
+                const int e = kQueue - qs + (lane < nq ? lane : 0);
+                map_queue<LDS_TABLE, false>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick);
                 qs -= nq;
                 wave_sync();
             }
@@ -1160,14 +1164,14 @@ __device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, co
                         wave_sync();
                         if (qf >= 64) {
                             const int e = qf - 64 + lane;
-                            map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm,
+                            map_queue<true, true, true>(A, e, true, qnode, qpk, P.a, c256, orient, tab8, bins, flgm,
                                                               thick, flgt, qdx, qdy, qdz);
                             qf -= 64;
                             wave_sync();
                         }
                         if (qs >= 64) {
                             const int e = kQueue - qs + lane;
-                            map_queue<true, false, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick,
+                            map_queue<true, false, true>(A, e, true, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick,
                                                          flgt);
                             qs -= 64;
                             wave_sync();
@@ -1183,16 +1187,16 @@ __device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, co
         while (qf > 0 || qs > 0) {
             if (qf > 0) {
                 const int nq = qf >= 64 ? 64 : qf;
-                const int e = lane < nq ? qf - nq + lane : -1;
-                map_queue<true, true, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt,
+                const int e = qf - nq + (lane < nq ? lane : 0);
+                map_queue<true, true, true>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt,
                                                   qdx, qdy, qdz);
                 qf -= nq;
                 wave_sync();
             }
             if (qs > 0) {
                 const int nq = qs >= 64 ? 64 : qs;
-                const int e = lane < nq ? kQueue - qs + lane : -1;
-                map_queue<true, false, true>(A, e, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt);
+                const int e = kQueue - qs + (lane < nq ? lane : 0);
+                map_queue<true, false, true>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt);
                 qs -= nq;
                 wave_sync();
             }
