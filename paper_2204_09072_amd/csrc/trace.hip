@@ -785,12 +785,13 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                     const int s2 = __mul24(s, s);
                     const bool accept = A.wide_open ? (int64_t)s2 * A.th_den2 < (int64_t)A.th_num2 * d2
                                                     : __umul24(s2, A.th_den2) < __umul24(A.th_num2, d2);
-                    const bool acc = valid && (leaf ? nid != tid : accept); // leaves always, but the target
-                    const bool opn = valid && !leaf && !accept;
-                    n_b += (valid && leaf && nid != tid) ? 1 : 0;
-                    n_h += (valid && !leaf && accept) ? 1 : 0;
+                    // (bitwise rather than short-circuit operators: no branches)
+                    const bool acc = valid & (leaf ? nid != tid : accept); // leaves always, but the target
+                    const bool opn = valid & !leaf & !accept;
+                    n_b += (valid & leaf & (nid != tid)) ? 1 : 0;
+                    n_h += (valid & !leaf & accept) ? 1 : 0;
                     n_open += opn ? 1 : 0;
-                    const int ext = acc && thick && A.merge ? (s >> 1) : 0;
+                    const int ext = (acc & thick & (A.merge != 0)) ? (s >> 1) : 0;
                     // One box test serves both kinds of node (a lane is opened or accepted, not
                     // both), in lattice units with R_i = i^2:
                     //  - an opened h-node keeps its subtree when r_max + s/4 >= R_a and
@@ -809,12 +810,12 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                     if (!COUNT) {
                         const int q4 = s >> 2;
                         const int lo = lo_cut - q4, hi = hi_cut + q4;
-                        keep = !(lo > 0 && rmax2 < __mul24(lo, lo)) && (last || rmin2 < __mul24(hi, hi));
+                        keep = !((lo > 0) & (rmax2 < __mul24(lo, lo))) & (last | (rmin2 < __mul24(hi, hi)));
                     }
-                    open = opn && keep;
+                    open = opn & keep;
                     push = ((uint32_t)nd.w << 3) | (uint32_t)(__builtin_popcount((nd.y >> 16) & 255) - 1);
                     if (!COUNT) {
-                        const bool maybe = acc && rmax2 >= a4 && (last || rmin2 < b4);
+                        const bool maybe = acc & (rmax2 >= a4) & (last | (rmin2 < b4));
                         const int dx = leaf ? vx * TR_FX : pfc.x - c256.x;
                         const int dy = leaf ? vy * TR_FX : pfc.y - c256.y;
                         const int dz = leaf ? vz * TR_FX : pfc.z - c256.z;
@@ -825,7 +826,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                             // r^2 exact in FP64 (a leaf's is 2^16 d2); the class is its binary
                             // exponent
                             const double r2 = (double)dx * dx + (double)dy * dy + (double)dz * dz;
-                            h.content = r2 >= PT.ta && (last || r2 < PT.tb);
+                            h.content = (r2 >= PT.ta) & (last | (r2 < PT.tb));
                             h.k0 = h.k1 = 0;
                             h.i = P.a + (r2 >= PT.t1 ? 1 : 0) + (r2 >= PT.t2 ? 1 : 0) + (r2 >= PT.t3 ? 1 : 0);
                             c = (__builtin_amdgcn_frexp_exp(r2) - 1) - 2 * (8 + log2s);
@@ -833,8 +834,8 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                             h = seg_hit(dx, dy, dz, s, ext, P.a, P.b, last, A.n_bins);
                             c = dist_class(dx, dy, dz, log2s);
                         }
-                        enq = maybe && (h.content || h.k1 > h.k0);
-                        far1 = enq && !A.per_node && c >= kAlphaFar;
+                        enq = maybe & (h.content | (h.k1 > h.k0));
+                        far1 = enq & (A.per_node == 0) & (c >= kAlphaFar);
                         pk = (h.content ? (uint32_t)(h.i - P.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
                              ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) | ((uint32_t)depth << 19) |
                              ((thick ? 1u : 0u) << 23) |
