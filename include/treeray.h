@@ -129,7 +129,8 @@ typedef struct tr_trace_params {
 /* Trace all cells of the tree: J (device float[n_cells], IRXE), F (device float[3][n],
  * flux), u_rad (device float[n_cells] = 4 pi J / c, or NULL).  Asynchronous; graph
  * capturable after the first call with the same N_side and cube_m (the first call builds
- * the angular-kernel table). */
+ * the angular-kernel table).  TR_EINVAL for a root edge above 2048 lattice units or a tree
+ * of 2^28 nodes or more (limits of the walk's integer tests and record offsets). */
 int tr_trace_rays(tr_ctx *ctx, const tr_tree *tree, const tr_trace_params *p, float *J,
                   float *F, float *u_rad);
 

@@ -117,6 +117,14 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// element i of an array, addressed as the array's (uniform) base plus a 32-bit byte offset,
+// which the hardware adds itself (no 64-bit address arithmetic per lane); every array read
+// this way is far below 4 GiB
+template <typename T>
+__device__ __forceinline__ const T &at32(const T *base, int i) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (uint32_t)i * (uint32_t)sizeof(T));
+}
+
 // largest i in [0, nb] with R_i + off <= r (lattice units / 256, R_i = 256 i^2), i.e.
 // (256 i^2 + off)^2 <= r2 or 256 i^2 + off <= 0.  Float estimate (hardware square root,
 // 1 ulp; the sum of squares adds a few more, far inside the 4e-6 r margin), exact
@@ -388,7 +396,7 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
         seg = valid ? (int)(pk & 63u) - 1 : -1;
         const uint32_t k0 = (pk >> 6) & 63u, k1 = (pk >> 12) & 63u;
         fbits = valid && k1 > k0 ? (k1 >= 32u ? 0xffffffffu : ((1u << k1) - 1u)) & ~((1u << k0) - 1u) : 0u;
-        const float4 qv = A.q[node];
+        const float4 qv = at32(A.q, node);
         auto lookup = [&](int cell) { return LDS_TABLE ? (int)tab8[cell] : (int)A.table[cell]; };
         unsigned long long en = 1ull << 61; // no entry: the per-node kernel
         int own = -1;                       // key served by the pixel table: the cell's pixel
@@ -400,14 +408,14 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
             beta = beta_of(dx, dy, dz, (seg > 0 ? seg : 0) + pass_a);
             const int key = alpha_key(dx, dy, dz, (int)(pk >> 24), orient, A.log2m, A.alpha_c1);
             // both reads, the one not needed at a harmless index, instead of a branch
-            const unsigned long long ek = A.alpha[key < 0 ? 0 : key];
+            const unsigned long long ek = at32(A.alpha, key < 0 ? 0 : key);
             const int ok = lookup(key < 0 ? -1 - key : 0);
             en = key < 0 ? 0ull : ek;
             own = key < 0 ? ok : -1;
             vkh = 0.0f;
             if (!leaf && ((pk >> 23) & 1u)) vkh = __int_as_float(A.pcol[node].w); // thick h-node (rare)
         } else {
-            const int4 p = A.pcol[node];
+            const int4 p = at32(A.pcol, node);
             vkh = __int_as_float(p.w);
             dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
             beta = beta_of(dx, dy, dz, (seg > 0 ? seg : 0) + pass_a);
@@ -771,10 +779,10 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                     // of branching (a lane without a node reads the root and keeps nothing).
                     const bool valid = node >= 0;
                     const int nid = valid ? node : 0;
-                    const int4 nd = A.nodes[nid];
+                    const int4 nd = at32(A.nodes, nid);
                     // mapping position, needed by accepted h-nodes: fetched beside the walk
                     // record rather than after the tests that depend on it
-                    const int4 pfc = A.pcol[nid];
+                    const int4 pfc = at32(A.pcol, nid);
                     const int depth = (nd.x >> 16) & 15;
                     const bool leaf = (nd.x >> 20) & 1;
                     const bool thick = (nd.x >> 21) & 1;
@@ -1460,6 +1468,9 @@ int setup_instance(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, floa
     if (t->n_bins > 63) return tr_fail(ctx, TR_EINVAL, "too many ray segments (%d)", t->n_bins);
     if (t->n_node >= ((int64_t)1 << 29)) return tr_fail(ctx, TR_EINVAL, "too many nodes for the walk stack");
     if (t->root_edge > 2048) return tr_fail(ctx, TR_EINVAL, "grid too fine for the walk's integer ranges");
+    if (t->n_node >= ((int64_t)1 << 28))
+        return tr_fail(ctx, TR_EINVAL, "tree of %lld nodes: the trace addresses node records with 32-bit offsets "
+                       "(at most 2^28 nodes)", (long long)t->n_node);
     if (t->n_cells >= ((int64_t)1 << 31)) return tr_fail(ctx, TR_EINVAL, "too many cells");
     if (t->ctx != ctx && t->ctx && t->ctx->device != ctx->device)
         return tr_fail(ctx, TR_EINVAL, "tree lives on another device");
