@@ -160,7 +160,8 @@ def dust_summary(stats):
             "speedup_learned_over_best_analytic_start": round(best_analytic / stats["learned"]["ms"], 3),
             "variants": stats,
             "stop_rule": "Newton step |dT| <= 1e-6 T (taken before the bracket test) or bracket width "
-                         "<= 1e-6 T, bracket-safeguarded"}
+                         "<= 1e-6 T; bisection when a step leaves the bracket, except that a step reaching an end not yet "
+                         "evaluated tries that end once"}
 
 
 def cpu_baseline(w, n_pix, stride, u_rad=None, gpu_t_dust=None):

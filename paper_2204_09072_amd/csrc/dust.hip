@@ -5,7 +5,8 @@
 //   C    = c_gd rho / (1.4 m_H)^2 sqrt(T_g) (1 - 0.8 exp(-75 / T_g)),
 // is strictly increasing, negative at min(T_g, T_J) and positive at max(T_g, T_J).
 // Newton's method (by default on ln w against ln T, see the kernel) runs inside that
-// bracket, with bisection when a step leaves it; the starting point is the bracket's secant
+// bracket, with bisection when a step leaves it (a step reaching an end not yet evaluated
+// tries that end first); the starting point is the bracket's secant
 // point in logarithms, the bracket end nearer the root, or the guess network's output.
 // Plain bisection of the same bracket is there as a reference for the step counts.
 #include "common.hpp"
@@ -79,8 +80,10 @@ __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
     } else {
         bool done = false;
         float wl = 0.0f;
+        bool lo_known = false, hi_known = false; // whether w has been evaluated at lo, hi
         if (START != START_LEARNED || lo == kFloor) {
             wl = wf(lo, dw);
+            lo_known = true;
             if (wl >= K) { T = lo; done = true; } // root at or below the lower end (floor)
         }
         if (!done) {
@@ -92,6 +95,7 @@ __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
                 T = 0.5f * (lo + hi);
             } else {
                 const float wh = wf(hi, dw);
+                hi_known = true;
                 const float rl = __logf(K) - __logf(wl), rh = __logf(wh) - __logf(K);
                 if (START == START_END) {
                     T = rl < rh ? lo : hi;
@@ -104,7 +108,13 @@ __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
             }
             for (it = 1; it <= A.max_iter; ++it) {
                 const float wv = wf(T, dw);
-                if (wv < K) lo = T; else hi = T;
+                if (wv < K) {
+                    lo = T;
+                    lo_known = true;
+                } else {
+                    hi = T;
+                    hi_known = true;
+                }
                 if (START == START_BISECT) {
                     T = 0.5f * (lo + hi);
                     if (hi - lo <= A.tol * hi) break;
@@ -118,7 +128,16 @@ __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
                     if (Tn > lo && Tn < hi) T = Tn;
                     break;
                 }
-                if (!(Tn > lo && Tn < hi)) Tn = 0.5f * (lo + hi);
+                // A step that reaches an end of the bracket where w has not been evaluated
+                // tries that end (once: it is then known).  Where the coupling is weak the
+                // root lies at T_J or T_gas to FP32 precision and Newton lands there from a
+                // good guess; bisection instead of that step took 10-16 steps.  Any other
+                // step outside the open bracket (or NaN) is replaced by bisection.
+                if (!(Tn > lo && Tn < hi)) {
+                    if (Tn >= hi && !hi_known) Tn = hi;
+                    else if (Tn <= lo && !lo_known) Tn = lo;
+                    else Tn = 0.5f * (lo + hi);
+                }
                 const bool conv = fabsf(Tn - T) <= A.tol * Tn || hi - lo <= A.tol * hi;
                 T = Tn;
                 if (conv) break;
