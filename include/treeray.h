@@ -111,10 +111,11 @@ typedef struct tr_trace_params {
     int32_t bins_per_pass; /* ray segments per walk pass (at most 16); 0 = automatic */
     int32_t chunk;         /* targets taken per work-queue grab; 0 = automatic */
     int32_t waves_per_block; /* waves per block; 0 = automatic */
-    int32_t kernel;        /* 0 = automatic, 1 = one wave per target (segments processed in
-                              passes of bins_per_pass radial points), 2 = one block of waves
-                              per target (all segments in LDS, one walk; needs N_side <= 4 and
-                              an opening angle >= 1/8) */
+    int32_t kernel;        /* 0 = automatic (currently always 1, the faster on every workload
+                              measured), 1 = one wave per target (segments processed in passes
+                              of bins_per_pass radial points), 2 = one block of waves per
+                              target (all segments in LDS, one walk; needs N_side <= 4 and an
+                              opening angle >= 1/8) */
     int32_t per_node_kernel; /* 0 = tabulated angular kernel (tr_alpha_table) for nodes at
                               least 8 edges away and the per-node 8-point kernel for nearer
                               ones; 1 = the per-node kernel for every node */

@@ -1439,10 +1439,13 @@ constexpr int kLdsCu = 160 * 1024;
 
 int table_bytes(int M) { return (6 * M * M + 15) & ~15; }
 int max_waves_for(int npix) { return npix > 192 ? 4 : 16; } // the kernel's launch bound
-// waves a CU holds at once for the kernel's register use (the wide-ray kernel, ~190
-// VGPRs, two per SIMD); passes are sized so that this many waves share the CU's LDS
-// (wide rays, 128^3 core: 2 segments per pass and 8 waves 13.6 s, 4 and 4 waves 23.3 s)
-int waves_cu_for(int npix) { return npix > 192 ? 8 : 16; }
+// waves a CU should hold at once; passes are sized so that this many waves share the CU's
+// LDS.  Wide rays (~190 VGPRs, two waves per SIMD): 8 (128^3 core, 2 segments per pass and
+// 8 waves 13.6 s, 4 and 4 waves 23.3 s).  Otherwise 16 for batches; a single tree takes 15:
+// on the 128^3 core the same 3 segments per pass as for 16 (and 16 waves still fit), on the
+// deeper AMR tree 3 instead of 2 (2.12 s against 2.19 s), while the 64-instance batch ran
+// 2 % slower with 15.
+int waves_cu_for(int npix, bool single = false) { return npix > 192 ? 8 : (single ? 15 : 16); }
 int nslot_for(int npix) { return npix <= 64 ? 1 : (npix <= 192 ? 3 : 12); }
 // the one-wave kernels keep the pixel table in LDS for up to 64 rays (N_side <= 2, at most
 // 6 KB); beyond that only near nodes read it, from global memory, and the LDS holds more
@@ -1590,19 +1593,15 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     const bool tab_lds = !count && table_in_lds(npix);
     const int lds_table = tab_lds ? table_bytes(I.M) : 0;
     const int max_waves = max_waves_for(npix);
-    // automatic choice: the one-block-per-target kernel when the one-wave kernel would need
-    // a dozen passes or more (it re-walks the tree for each); below that the one-wave kernel
-    // is at least as fast on the MI355X (128^3 core, 7 passes: 1.63 s vs 1.74 s; AMR
-    // 256^3-equivalent, 15 passes: 2.60 s vs 2.36 s)
-    const bool many_passes =
-        tr_div_up(I.A.n_bins, choose_bp(I, p->bins_per_pass, lds_table, waves_cu_for(npix), count)) >= 12;
-    if (!count && (p->kernel == 2 || (p->kernel == 0 && many_passes))) {
+    // the one-block-per-target kernel only on request: the one-wave kernel is faster on every
+    // workload measured (128^3 core 1.46 s against 1.75 s; AMR 256^3-equivalent, 10 passes,
+    // 2.12 s against 2.30 s for one pass per target)
+    if (!count && p->kernel == 2) {
         rc = launch_coop(ctx, I, p, npix <= 256 ? table_bytes(I.M) : 0);
         if (rc != TR_ENOTSUP) return rc;
-        if (p->kernel == 2) return tr_fail(ctx, TR_EINVAL, "the one-block-per-target kernel does not fit this case");
-        ctx->err.clear();
+        return tr_fail(ctx, TR_EINVAL, "the one-block-per-target kernel does not fit this case");
     }
-    set_bp(I, choose_bp(I, p->bins_per_pass, lds_table, waves_cu_for(npix), count), count);
+    set_bp(I, choose_bp(I, p->bins_per_pass, lds_table, waves_cu_for(npix, true), count), count);
     TraceArgs &A = I.A;
     A.chunk = p->chunk > 0 ? p->chunk : 1; // one target per grab: a short tail (128^3 core: 1.59 s, 1.61 s with 4)
     A.lds_table = lds_table;
