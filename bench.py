@@ -263,9 +263,10 @@ def trace_counters(paths):
     return {c: float(np.mean(x)) for c, x in sorted(rows.items())}
 
 
-def write_traffic(workload, fetch_paths, write_paths, calib_bytes, out_paths):
+def write_traffic(workload, fetch_paths, write_paths, calib_bytes, out_paths, tcc_paths=None):
     """HBM bytes per trace launch from FETCH_SIZE and WRITE_SIZE runs of --traffic-probe,
-    each scaled by the same counter's reading for a plain copy of known size."""
+    each scaled by the same counter's reading for a plain copy of known size; with a
+    TCC_HIT_sum / TCC_MISS_sum run also the launch's L2 hit rate."""
     def pick(paths, counter):
         d = pmc_per_dispatch(paths)
         trace = [v[counter] for (k, _), v in d.items() if "k_trace<" in k and "true" not in k.split(",")[1]]
@@ -281,6 +282,9 @@ def write_traffic(workload, fetch_paths, write_paths, calib_bytes, out_paths):
             "copy_bytes": calib_bytes, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
             "fetch_scale": kf, "write_scale": kw,
             "bytes_per_launch": f_trace * 1024.0 * kf + w_trace * 1024.0 * kw}
+    if tcc_paths:
+        cs = trace_counters(tcc_paths)
+        info["l2_hit_rate"] = cs["TCC_HIT_sum"] / (cs["TCC_HIT_sum"] + cs["TCC_MISS_sum"])
     for p in out_paths:
         with open(p, "w") as f:
             json.dump(info, f, indent=1)
@@ -389,6 +393,8 @@ def main():
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/trace_<workload>_traffic.json from two --pmc runs")
     ap.add_argument("--traffic-out", nargs="*", default=None)
+    ap.add_argument("--tcc", nargs="*", default=None, metavar="DIR",
+                    help="with --write-traffic: a TCC_HIT_sum TCC_MISS_sum run for the L2 hit rate")
     ap.add_argument("--ray-study", action="store_true",
                     help="trace cost and T_J accuracy at 48, 192 and 768 rays (prints one JSON line)")
     args = ap.parse_args()
@@ -408,11 +414,11 @@ def main():
     if args.write_traffic:
         outs = args.traffic_out or [os.path.join(ROOT, "profiles", f"trace_{args.workload}_traffic.json")]
         print(json.dumps(write_traffic(args.workload, [args.write_traffic[0]], [args.write_traffic[1]],
-                                       CALIB_BYTES, outs)))
+                                       CALIB_BYTES, outs, args.tcc)))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; run it with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.traffic_probe:
@@ -504,15 +510,17 @@ def main():
     alg_bytes = float(B_LEAF * c[0] + B_HNODE * (c[1] + c[2]))
     t_trace = float(np.mean(times["trace"])) / 1000.0
     achieved = alg_bytes / t_trace / 1e9
-    traffic = None
+    traffic = l2_hit = None
     tj = os.path.join(ROOT, "profiles", f"trace_{args.workload}_traffic.json")
     if os.path.exists(tj):
         with open(tj) as f:
             tr_info = json.load(f)
         if tr_info.get("trace_hip_sha") == kernel_source_hash():
             traffic = tr_info.get("bytes_per_launch")
+            l2_hit = tr_info.get("l2_hit_rate")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
             "frac": round(achieved / 8000.0, 4), "traffic": traffic,
+            "l2_hit_rate": None if l2_hit is None else round(l2_hit, 4),
             "kernel": "k_trace", "algorithmic_bytes_per_launch": alg_bytes,
             "kernel_ms": round(t_trace * 1000, 3),
             "walk_totals": {"b_nodes_accepted": int(c[0]), "h_nodes_accepted": int(c[1]),
