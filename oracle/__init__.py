@@ -51,6 +51,11 @@ def lib():
         L.or_pix2vec.argtypes = [C.c_int, C.c_int, P]
         L.or_vec2pix.restype = C.c_int
         L.or_vec2pix.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+        L.or_vec2pix_many.argtypes = [C.c_int, C.c_int64, P, P]
+        L.or_march.restype = C.c_double
+        L.or_march.argtypes = [C.c_int, C.c_double, P, P, P, P, C.c_int, P]
+        L.or_march_mean.argtypes = [C.c_int, C.c_double, P, P, C.c_int64, P, C.c_int, C.c_int,
+                                    C.c_int, P, P]
         L.or_cube_table.argtypes = [C.c_int, C.c_int, P]
         L.or_alpha_table.argtypes = [C.c_int, P, P]
         L.or_trace.restype = C.c_int
@@ -191,6 +196,41 @@ def ray_dirs(n_side):
 
 def vec2pix(n_side, v):
     return lib().or_vec2pix(int(n_side), float(v[0]), float(v[1]), float(v[2]))
+
+
+def vec2pix_many(n_side, v):
+    """Pixel ids of directions v [n, 3]."""
+    v = np.ascontiguousarray(v, np.float64).reshape(-1, 3)
+    out = np.zeros(v.shape[0], np.int32)
+    lib().or_vec2pix_many(int(n_side), v.shape[0], _p(v), _p(out))
+    return out
+
+
+def march(kr, B, box, p, u, skip_own=False):
+    """Direct ray marching (no tree) through dense [n, n, n] arrays (index [i, j, k] along
+    x, y, z) of rho*kappa per length and source function: (intensity, optical depth)."""
+    kr = np.ascontiguousarray(kr, np.float64)
+    B = np.ascontiguousarray(B, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    u = np.ascontiguousarray(u, np.float64)
+    tau = np.zeros(1)
+    I = lib().or_march(int(kr.shape[0]), float(box), _p(kr), _p(B), _p(p), _p(u), int(bool(skip_own)),
+                       _p(tau))
+    return I, tau[0]
+
+
+def march_mean(kr, B, box, pts, n_side, sub=3, skip_own=False):
+    """Mean intensity J and mean absorbed fraction <1 - e^-tau> at each point of pts [m, 3]
+    by direct marching along the 4^sub sub-pixels of every pixel of the N_side set."""
+    kr = np.ascontiguousarray(kr, np.float64)
+    B = np.ascontiguousarray(B, np.float64)
+    pts = np.ascontiguousarray(pts, np.float64).reshape(-1, 3)
+    m = pts.shape[0]
+    J = np.zeros(m)
+    A = np.zeros(m)
+    lib().or_march_mean(int(kr.shape[0]), float(box), _p(kr), _p(B), m, _p(pts), int(n_side), int(sub),
+                        int(bool(skip_own)), _p(J), _p(A))
+    return J, A
 
 
 def cube_table(n_side, M=None):

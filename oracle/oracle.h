@@ -80,6 +80,20 @@ int or_trace_one(const or_tree *t, const or_params *p, int64_t cell, int brute,
 double or_integrate_ray(int n_side, int n_bins, const double *bins, const uint8_t *flags,
                         double j_bg);
 
+/* Direct ray marching through a uniform n^3 grid over [0, box)^3 without the tree (the
+ * brute-force reference of the method's end-to-end error).  kr = rho kappa per length and
+ * B = source function, dense [(i n + j) n + k]; returns the intensity along unit vector u
+ * from point p, *tau_out the optical depth to the grid's edge.  skip_own: the start cell
+ * neither absorbs nor emits. */
+double or_march(int n, double box, const double *kr, const double *B, const double *p,
+                const double *u, int skip_own, double *tau_out);
+/* Mean over the 4^sub NESTED sub-pixels of every pixel of the N_side = ns set: J[n_pt]
+ * (mean intensity) and absorbed[n_pt] (mean of 1 - e^-tau); either may be NULL. */
+void or_march_mean(int n, double box, const double *kr, const double *B, int64_t n_pt,
+                   const double *pts, int ns, int sub, int skip_own, double *J, double *absorbed);
+/* pixel ids of n directions [n][3] */
+void or_vec2pix_many(int n_side, int64_t n, const double *v, int32_t *out);
+
 /* Radiation-pressure acceleration a[n][3] and trapped pressure p_src[n] (Sec. 4.5). */
 void or_rad_force(const or_tree *t, const float *rho, const float *kappa,
                   const float *t_dust, const double *F, double c, double *a, double *p_src);
@@ -102,7 +116,7 @@ void or_uv_rad_pressure(int64_t n, const double *rho, const double *x_ion, const
                         const double *uph, double e_ph, double sigma_d, double sigma_h, double alpha_b,
                         double mu_mh, double c, double *a, double *parts);
 
-/* MLP 3 -> H -> H -> 1 (tanh), FP64 forward and backward for a batch; parameter
+/* MLP 3 -> H -> H -> 1 (ReLU hidden layers), FP64 forward and backward for a batch; parameter
  * layout W1[H][3] b1[H] W2[H][H] b2[H] W3[H] b3.  round_bf16 != 0 rounds each layer's
  * input activations to bfloat16 (as the GPU's MFMA operands).  Returns the mean
  * squared error; grad (same layout) may be NULL; out[n] may be NULL. */

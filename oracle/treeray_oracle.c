@@ -881,6 +881,97 @@ int or_trace_one(const or_tree *t, const or_params *p, int64_t cell, int brute, 
 }
 
 /* ------------------------------------------------------------------------------------
+ * Direct ray marching without the tree: a brute-force reference for the method's
+ * end-to-end error (the tree walk, the radial and angular kernels and the segment
+ * integration of Sec. 4.2-4.3 are all bypassed).  A ray from point p along the unit
+ * vector u crosses the cells of a uniform n^3 grid over [0, box)^3 one by one (the
+ * cell-stepping traversal of Amanatides & Woo 1987); a crossing of length l through a
+ * cell of absorption coefficient k (= rho kappa, per unit length) and source function B
+ * adds B (1 - e^{-k l}) e^{-tau} to the intensity (the formal solution of the transfer
+ * equation of Sec. 2 for a piecewise constant medium) and k l to the optical depth tau.
+ * Dense cell arrays are indexed (i n + j) n + k for the cell (i, j, k) along (x, y, z).
+ * skip_own: the start cell neither absorbs nor emits (the reading of the target's own
+ * segment, which carries nothing in the tree method).
+ * ---------------------------------------------------------------------------------- */
+double or_march(int n, double box, const double *kr, const double *B, const double *p,
+                const double *u, int skip_own, double *tau_out) {
+    const double dx = box / n;
+    int64_t c[3];
+    int step[3];
+    double tmax[3], tdel[3];
+    for (int a = 0; a < 3; ++a) {
+        c[a] = (int64_t)floor(p[a] / dx);
+        if (c[a] < 0) c[a] = 0;
+        if (c[a] > n - 1) c[a] = n - 1;
+        if (u[a] > 0.0) {
+            step[a] = 1;
+            tmax[a] = ((double)(c[a] + 1) * dx - p[a]) / u[a];
+            tdel[a] = dx / u[a];
+        } else if (u[a] < 0.0) {
+            step[a] = -1;
+            tmax[a] = ((double)c[a] * dx - p[a]) / u[a];
+            tdel[a] = -dx / u[a];
+        } else {
+            step[a] = 0;
+            tmax[a] = INFINITY;
+            tdel[a] = INFINITY;
+        }
+    }
+    double t = 0.0, tau = 0.0, I = 0.0;
+    int first = 1;
+    for (;;) {
+        int a = 0;
+        if (tmax[1] < tmax[a]) a = 1;
+        if (tmax[2] < tmax[a]) a = 2;
+        const double l = tmax[a] - t;
+        if (!(first && skip_own) && l > 0.0) {
+            const int64_t id = (c[0] * n + c[1]) * n + c[2];
+            const double dt = kr[id] * l;
+            I += B[id] * (-expm1(-dt)) * exp(-tau);
+            tau += dt;
+        }
+        first = 0;
+        t = tmax[a];
+        c[a] += step[a];
+        if (c[a] < 0 || c[a] >= n) break;
+        tmax[a] += tdel[a];
+    }
+    if (tau_out) *tau_out = tau;
+    return I;
+}
+
+/* Mean intensity at each of n_pt points from direct marching: every ray h of the
+ * N_side = ns HEALPix set is sampled by its 4^sub NESTED sub-pixels at N_side ns 2^sub
+ * (equal-area, so the plain mean over them is the pixel average), J = the mean of the
+ * intensities over all of them.  esc_out[n_pt] (may be NULL) receives the mean of
+ * 1 - e^{-tau} over the same directions (the absorbed fraction of a point source's
+ * light). */
+void or_march_mean(int n, double box, const double *kr, const double *B, int64_t n_pt,
+                   const double *pts, int ns, int sub, int skip_own, double *J, double *absorbed) {
+    const int64_t nsub = (int64_t)1 << (2 * sub), nfine = 12 * (int64_t)ns * ns * nsub;
+    const int nsf = ns << sub;
+    double *dirs = (double *)malloc(sizeof(double) * 3 * nfine);
+    for (int64_t q = 0; q < nfine; ++q) or_pix2vec(nsf, (int)q, dirs + 3 * q);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < n_pt; ++k) {
+        double sI = 0.0, sA = 0.0;
+        for (int64_t q = 0; q < nfine; ++q) {
+            double tau;
+            sI += or_march(n, box, kr, B, pts + 3 * k, dirs + 3 * q, skip_own, &tau);
+            sA += -expm1(-tau);
+        }
+        if (J) J[k] = sI / (double)nfine;
+        if (absorbed) absorbed[k] = sA / (double)nfine;
+    }
+    free(dirs);
+}
+
+/* pixel of each of n directions [n][3] */
+void or_vec2pix_many(int ns, int64_t n, const double *v, int32_t *out) {
+    for (int64_t k = 0; k < n; ++k) out[k] = or_vec2pix(ns, v[3 * k], v[3 * k + 1], v[3 * k + 2]);
+}
+
+/* ------------------------------------------------------------------------------------
  * Radiation pressure (Sec. 4.5): a = kappa F / c * (1 - e^-tau) / tau with the factor
  * taken as 1 below tau = 1e-4; trapped pressure of a hosted source uses the host
  * cell's face area dV^(2/3).
