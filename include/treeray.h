@@ -279,6 +279,11 @@ int tr_uv_rad_pressure(tr_ctx *ctx, int64_t n, const float *rho, const float *x_
 int tr_ctx_create(tr_ctx **out, int device, void *stream);
 void tr_ctx_destroy(tr_ctx *ctx);
 int tr_ctx_set_stream(tr_ctx *ctx, void *stream);
+/* Input validation (off by default): when on, tr_build_tree checks every cell's rho, kappa (if
+ * given) and t_dust and fails with TR_EINVAL, building nothing, if any is negative, infinite or
+ * NaN (the paper's densities, opacities and temperatures are finite and non-negative, Sec. 2,
+ * 4.1).  The check is one extra kernel before the build's single synchronisation. */
+int tr_ctx_set_validation(tr_ctx *ctx, int on);
 const char *tr_last_error(const tr_ctx *ctx);
 /* Wait for the stream and report latched device-side failures (TR_EOVERFLOW). */
 int tr_sync(tr_ctx *ctx);

@@ -80,6 +80,7 @@ _I = C.c_int
 _sig("tr_ctx_create", _I, [C.POINTER(_P), _I, _P])
 _sig("tr_ctx_destroy", None, [_P])
 _sig("tr_ctx_set_stream", _I, [_P, _P])
+_sig("tr_ctx_set_validation", _I, [_P, _I])
 _sig("tr_last_error", C.c_char_p, [_P])
 _sig("tr_sync", _I, [_P])
 _sig("tr_build_tree", _I, [_P, C.POINTER(Grid), _P, _P, _P, _P, _I, C.POINTER(Units), C.POINTER(_P)])
@@ -144,6 +145,9 @@ class Context:
 
     def set_stream(self, stream):
         self.check(_lib.tr_ctx_set_stream(self.h, _P(stream)))
+
+    def set_validation(self, on: bool):
+        self.check(_lib.tr_ctx_set_validation(self.h, int(bool(on))))
 
     def sync(self):
         self.check(_lib.tr_sync(self.h))

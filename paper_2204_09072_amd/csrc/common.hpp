@@ -31,6 +31,7 @@ struct tr_ctx {
     hipStream_t stream = nullptr;
     int n_cu = 0;
     std::string err;
+    int validate = 0; // tr_build_tree checks its cell arrays (tr_ctx_set_validation)
     // device scratch: [0..7] work counters, [16] trace error word, [17] tree error word,
     // [24] largest relative change of a fixed-point sweep
     int *d_ctl = nullptr;

@@ -54,6 +54,12 @@ extern "C" int tr_ctx_set_stream(tr_ctx *c, void *stream) {
     return TR_OK;
 }
 
+extern "C" int tr_ctx_set_validation(tr_ctx *c, int on) {
+    if (!c) return TR_EINVAL;
+    c->validate = on ? 1 : 0;
+    return TR_OK;
+}
+
 extern "C" const char *tr_last_error(const tr_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 extern "C" int tr_sync(tr_ctx *c) {

@@ -68,6 +68,19 @@ __global__ void k_exist(int d, DenseLayout L, uint32_t *__restrict__ occ, int *_
     occ[L.base[d] + m] = v;
 }
 
+// Optional input check (tr_ctx_set_validation): a density, opacity or dust temperature that
+// is not a finite number >= 0 sets bit 8, 9 or 10 of the build's error word.
+__global__ void k_validate_cells(int64_t n, const float *__restrict__ rho, const float *__restrict__ kappa,
+                                 const float *__restrict__ t_dust, int *__restrict__ err) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    auto bad = [](float v) { return !(v >= 0.0f && v <= 3.402823466e38f); }; // NaN fails both
+    int e = bad(rho[c]) ? 256 : 0;
+    if (kappa && bad(kappa[c])) e |= 512;
+    if (bad(t_dust[c])) e |= 1024;
+    if (e) atomicOr(err, e);
+}
+
 struct ExistsOp {
     __device__ int operator()(uint32_t v) const { return v != 0u ? 1 : 0; }
 };
@@ -358,6 +371,8 @@ extern "C" int tr_build_tree(tr_ctx *ctx, const tr_grid *grid, const float *rho,
         return tr_fail(ctx, TR_EHIP, "tr_build_tree: upload failed");
     }
     const int TPB = 256;
+    if (ctx->validate)
+        k_validate_cells<<<tr_div_up(t->n_cells, TPB), TPB, 0, st>>>(t->n_cells, rho, kappa, t_dust, err);
     k_mark_leaves<<<tr_div_up(t->n_cells, TPB), TPB, 0, st>>>(d_blocks, t->n_cells, D, t->max_level, L, occ, err);
     for (int d = D - 1; d >= 0; --d)
         k_exist<<<tr_div_up((int64_t)1 << (3 * d), TPB), TPB, 0, st>>>(d, L, occ, err);
@@ -389,6 +404,11 @@ extern "C" int tr_build_tree(tr_ctx *ctx, const tr_grid *grid, const float *rho,
         hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
         cleanup(); return tr_fail(ctx, TR_EHIP, "readback failed");
+    }
+    if (herr & 1792) {
+        cleanup();
+        return tr_fail(ctx, TR_EINVAL, "tr_build_tree: a cell's %s is negative, infinite or NaN",
+                       (herr & 256) ? "density" : ((herr & 512) ? "opacity" : "dust temperature"));
     }
     if (herr) { cleanup(); return tr_fail(ctx, TR_EINVAL, "blocks overlap (code %d)", herr); }
     t->n_node = last_id + (last_occ != 0u ? 1 : 0);

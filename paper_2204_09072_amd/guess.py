@@ -20,7 +20,10 @@ def train_guess(ctx: Context, rho, u_rad, t_gas, t_dust, steps=3000, batch=8192,
                 seed=0, log_every=0):
     """Fit the network to (rho, u_rad, T_gas) -> T_dust samples (host arrays).
 
-    Returns (mlp, losses).  The learning rate decays by 10x over the run."""
+    Mini-batches are consecutive slices of the samples in an order drawn on the host once
+    per pass over the data (a fresh permutation, uploaded whole); every training step runs
+    in the library (tr_mlp_train_step).  Returns (mlp, losses).  The learning rate decays
+    by 10x over the run."""
     import torch
     f = features(np.asarray(rho, np.float64), np.asarray(u_rad, np.float64),
                  np.asarray(t_gas, np.float64))
@@ -29,20 +32,24 @@ def train_guess(ctx: Context, rho, u_rad, t_gas, t_dust, steps=3000, batch=8192,
     scale = 1.0 / np.maximum(f.std(axis=0), 1e-6)
     oshift, oscale = y.mean(), 1.0 / max(y.std(), 1e-6)
     norm = np.array([*shift, *scale, oshift, oscale], np.float32)
-    x = torch.from_numpy(((f - shift) * scale).astype(np.float32)).cuda()
-    t = torch.from_numpy(((y - oshift) * oscale).astype(np.float32)).cuda()
+    xs = ((f - shift) * scale).astype(np.float32)
+    ys = ((y - oshift) * oscale).astype(np.float32)
     mlp = Mlp(ctx, init_mlp_params(seed), norm)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
+    rng = np.random.default_rng(seed)
     loss = torch.zeros(1, device="cuda")
     losses = []
-    n = x.shape[0]
+    n = ys.shape[0]
+    batch = min(batch, n)
+    per_pass = n // batch
+    x = t = None
     for s in range(steps):
-        idx = torch.randint(0, n, (batch,), device="cuda", generator=gen)
-        xb = x.index_select(0, idx).contiguous()
-        yb = t.index_select(0, idx).contiguous()
+        k = s % per_pass
+        if k == 0:
+            order = rng.permutation(n)
+            x = torch.from_numpy(np.ascontiguousarray(xs[order])).cuda()
+            t = torch.from_numpy(np.ascontiguousarray(ys[order])).cuda()
         a = lr * (0.1 ** (s / max(steps - 1, 1)))
-        mlp.train_step(xb, yb, a, loss)
+        mlp.train_step(x[k * batch:(k + 1) * batch], t[k * batch:(k + 1) * batch], a, loss)
         if log_every and (s % log_every == 0 or s == steps - 1):
             ctx.sync()
             losses.append((s, float(loss.item())))

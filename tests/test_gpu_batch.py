@@ -130,3 +130,35 @@ def test_batch_rejects_bad_input(lib, ctx, batch_setup):
     bad[1] = lib.trace_params(3)
     with pytest.raises(lib.TreerayError):
         lib.Batch(ctx, trees, bad, J, F, U)
+
+
+def test_batch_full_size_c4_sampled(lib, ctx):
+    """The whole 64-instance batch at full size (edges 32-96 in steps of 8, lognormal
+    densities, 0-4 stars, N_side 2 or 4: 24.1 M cells) in one graph-replayed persistent
+    launch; ten sampled targets of every instance against the oracle."""
+    import torch
+    from paper_2204_09072_amd.run import params_of, tree_of, upload
+    ws = W.c4_batch64()
+    trees, J, F, U, devs = [], [], [], [], []
+    for w in ws:
+        devs.append(upload(w))
+        trees.append(tree_of(ctx, w, devs[-1]))
+        n = trees[-1].n_cells
+        J.append(torch.full((n,), -1.0, device="cuda"))
+        F.append(torch.full((3, n), -1.0, device="cuda"))
+        U.append(torch.full((n,), -1.0, device="cuda"))
+    say("c4 batch", len(ws), "instances,", sum(t.n_cells for t in trees), "cells")
+    b = lib.Batch(ctx, trees, [params_of(w) for w in ws], J, F, U)
+    b.launch()
+    ctx.sync()
+    say("c4 batch traced")
+    rng = np.random.default_rng(14)
+    for k, w in enumerate(ws):
+        cells = np.sort(rng.choice(w.n_cells, 10, replace=False))
+        Jo, Fo = oracle.Tree(w).trace(oracle.params(w.n_side, theta=w.theta), cells=cells)
+        _check_trace(J[k].cpu().numpy()[cells], F[k].cpu().numpy().T[cells], Jo, Fo)
+        u = U[k].cpu().numpy()[cells]
+        assert np.allclose(u, 4 * np.pi * J[k].cpu().numpy()[cells] / w.units[1], rtol=1e-6)
+    b.free()
+    for t in trees:
+        t.free()

@@ -253,7 +253,25 @@ def test_trace_parity_nside8_sampled(lib, ctx):
     _check_trace(J.cpu().numpy()[cells], F.cpu().numpy().T[cells], Jo, Fo)
 
 
+def _force_factor(ot, c):
+    """(kappa / c) phi_RP(tau) of every cell: the oracle's force for a unit flux (Sec. 4.5)."""
+    return ot.rad_force(np.ones((ot.n_cells, 3)), c)[0][:, 0]
+
+
+def _check_force(a, ps, ao, po, fac, Jo, cells=None):
+    """a_RP per cell and component within 1e-4 (kappa / c) phi_RP 4 pi J of that cell (the
+    flux bar carried through the force); P_src per cell within 1e-5 relative."""
+    sel = slice(None) if cells is None else cells
+    tol = 1e-4 * fac[sel, None] * 4 * np.pi * np.abs(Jo)[:, None]
+    d = np.abs(np.asarray(a, np.float64) - ao[sel])
+    assert (d <= tol + 1e-37).all(), f"a_RP: worst {np.max(d / (tol + 1e-37)):.3e} x tolerance"
+    po = po[sel]
+    assert (np.abs(np.asarray(ps, np.float64) - po) <= 1e-5 * np.abs(po)).all()
+
+
 def test_rad_force_parity(lib, ctx):
+    """The whole path (trace, then force) against the oracle's whole path, per cell and
+    component; and the force step alone on the library's own flux, per element."""
     from paper_2204_09072_amd.run import force, trace
     w = TREE_CASES["padded40"]()
     say("rad force")
@@ -261,12 +279,65 @@ def test_rad_force_parity(lib, ctx):
     a, ps = force(ctx, tree, F)
     ctx.sync()
     ot = oracle.Tree(w)
-    ao, po = ot.rad_force(F.cpu().numpy().T.astype(np.float64), w.units[1])
+    Jo, Fo = ot.trace(oracle.params(w.n_side, theta=w.theta))
+    ao, po = ot.rad_force(Fo, w.units[1])
+    fac = _force_factor(ot, w.units[1])
     a = a.cpu().numpy().T
-    scale = np.abs(ao).max(axis=1, keepdims=True) + 1e-30
-    assert np.abs(a - ao).max() <= 1e-5 * np.abs(ao).max()
-    assert np.allclose(ps.cpu().numpy(), po, rtol=1e-5, atol=0)
+    ps = ps.cpu().numpy()
+    _check_force(a, ps, ao, po, fac, Jo)
     assert (po > 0).sum() == 2
+    # the force step alone, given the same flux: a = kappa F / c phi_RP per element
+    ag, pg = ot.rad_force(F.cpu().numpy().T.astype(np.float64), w.units[1])
+    assert (np.abs(a - ag) <= 1e-5 * np.abs(ag) + 1e-37).all()
+    assert (np.abs(ps - pg) <= 1e-5 * pg).all()
+
+
+@pytest.mark.parametrize("name,n_sample", [("core128", 120), ("amr256", 200)])
+def test_rad_force_parity_full_size_sampled(lib, ctx, name, n_sample):
+    """a_RP of sampled cells of the full-size core and AMR grid, trace and force on the GPU
+    against the oracle's trace and force, per cell and component."""
+    from paper_2204_09072_amd.run import force, trace
+    w = W.CONFIGS[name]()
+    say("rad force full size", name, w.n_cells)
+    tree, J, F, U = trace(ctx, w)
+    a, ps = force(ctx, tree, F)
+    ctx.sync()
+    cells = np.sort(np.random.default_rng(13).choice(w.n_cells, n_sample, replace=False))
+    ot = oracle.Tree(w)
+    Jo, Fo = ot.trace(oracle.params(w.n_side, theta=w.theta), cells=cells)
+    Ff = np.zeros((w.n_cells, 3))
+    Ff[cells] = Fo
+    ao, po = ot.rad_force(Ff, w.units[1])
+    fac = _force_factor(ot, w.units[1])
+    _check_force(a.cpu().numpy().T[cells], ps.cpu().numpy()[cells], ao, po, fac, Jo, cells)
+
+
+def test_build_tree_validates_cells_on_request(lib, ctx):
+    """With validation on, a NaN, infinite or negative density, opacity or dust temperature
+    makes the build fail with TR_EINVAL; off (the default), the same arrays build."""
+    import torch
+    from paper_2204_09072_amd.run import upload
+    w = W.small_uniform(16, 1.0, 1.0, 1.0)
+    dev = upload(w)
+    say("build validation")
+    args = lambda d: (ctx, w.nb, 0, w.blocks, w.x0, 1.0, d["rho"], d["kappa"], d["t_dust"], w.stars, np.pi, 1.0)
+    ctx.set_validation(True)
+    try:
+        lib.build_tree(*args(dev)).free()
+        for field, val in (("rho", float("nan")), ("rho", -1.0), ("kappa", float("inf")), ("t_dust", -0.5)):
+            d = dict(dev)
+            d[field] = dev[field].clone()
+            d[field][777] = val
+            with pytest.raises(lib.TreerayError) as e:
+                lib.build_tree(*args(d))
+            assert e.value.code == lib.TR_EINVAL
+            assert {"rho": "density", "kappa": "opacity", "t_dust": "dust temperature"}[field] in str(e.value)
+    finally:
+        ctx.set_validation(False)
+    d = dict(dev)
+    d["rho"] = dev["rho"].clone()
+    d["rho"][777] = -1.0
+    lib.build_tree(*args(d)).free()
 
 
 def test_build_tree_rejects_bad_grids(lib, ctx):
@@ -351,3 +422,39 @@ def test_mlp_grad_parity(lib, ctx):
         err = np.linalg.norm(g[a:b] - go[a:b]) / max(np.linalg.norm(go[a:b]), 1e-30)
         say("grad block", a, b, "rel frobenius err %.2e" % err)
         assert err < 1e-2, (a, b, err)
+
+
+def test_mlp_adam_steps_match_closed_form(lib, ctx):
+    """Two training steps against Adam's update written out in numpy (beta1 0.9, beta2 0.999,
+    eps 1e-8, bias-corrected moments), each fed the gradient the library computes for the
+    same parameters and batch."""
+    import torch
+    prm = lib.init_mlp_params(5)
+    rng = np.random.default_rng(6)
+    m = lib.Mlp(ctx, prm)
+    lr = 1e-2
+    p = prm.astype(np.float64)
+    mom = np.zeros_like(p)
+    vel = np.zeros_like(p)
+    say("adam steps")
+    for step in (1, 2):
+        x = torch.from_numpy(rng.normal(size=(3000, 3)).astype(np.float32)).cuda()
+        y = torch.from_numpy(rng.normal(size=3000).astype(np.float32)).cuda()
+        g = torch.zeros(lib.MLP_NPARAM, device="cuda")
+        loss = torch.zeros(1, device="cuda")
+        m.grad(x, y, g, loss)
+        ctx.sync()
+        g = g.cpu().numpy().astype(np.float64)
+        m.train_step(x, y, lr)
+        ctx.sync()
+        mom = 0.9 * mom + 0.1 * g
+        vel = 0.999 * vel + 0.001 * g * g
+        upd = lr * (mom / (1 - 0.9 ** step)) / (np.sqrt(vel / (1 - 0.999 ** step)) + 1e-8)
+        p = p - upd
+        got = m.params().astype(np.float64)
+        err = np.abs(got - p)
+        # the step size is lr * O(1); the gradient's own rounding (atomic order) moves it by
+        # far less except where |g| ~ eps
+        assert (err <= 1e-3 * lr + 1e-6 * np.abs(p)).all(), (step, err.max())
+        assert np.abs(upd).max() > 0.5 * lr
+    m.free()

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
 
 
-def test_binding_structs_match_header():
+def test_binding_structs_match_header(tmp_path):
     """Compile a host probe against the header and compare struct sizes and offsets with
     the ctypes mirrors of the binding."""
     if not os.path.exists(LIB):
@@ -51,9 +51,8 @@ int main(void) {
   return 0;
 }
 '''
-    d = os.path.join(ROOT, "_work") if os.path.isdir(os.path.join(ROOT, "_work")) else "/tmp"
-    src = os.path.join(d, "abi_probe.c")
-    exe = os.path.join(d, "abi_probe")
+    src = str(tmp_path / "abi_probe.c")
+    exe = str(tmp_path / "abi_probe")
     with open(src, "w") as f:
         f.write(probe)
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
