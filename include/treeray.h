@@ -213,6 +213,20 @@ int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, const float *u
                         const float *t_gas, const tr_dust_params *p, const tr_mlp *mlp,
                         float *t_dust, uint8_t *iters);
 
+/* Allocation-free variant of tr_dust_equilibrium, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results, but the guess network's starting
+ * temperatures go to a fixed scratch array of TR_NOALLOC_DUST_STATES floats (16 MiB) that each
+ * GPU holds from the library's first context on it until the process ends.  n above
+ * TR_NOALLOC_DUST_STATES fails with TR_EINVAL before any work; the call makes no hipMalloc or
+ * hipFree.  Every call on one GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (other streams or contexts) race, and the caller must order them.  Nothing in the array
+ * has to start at zero: the network writes every starting point the solve then reads. */
+#define TR_NOALLOC_DUST_STATES (1 << 22)
+int tr_dust_equilibrium_noalloc(tr_ctx *ctx, int64_t n, const float *rho, const float *u_rad,
+                                const float *t_gas, const tr_dust_params *p, const tr_mlp *mlp,
+                                float *t_dust, uint8_t *iters);
+
 /* Self-consistent dust temperature (Sec. 2, 4.1, 4.6): repeat tree build (Planck-mean
  * opacity and emission of the current T_dust; no kappa array), ray tracing and dust
  * equilibrium until the largest relative change of T_dust is <= tol or max_iter sweeps.

@@ -104,6 +104,7 @@ _sig("tr_dust_fixed_point", _I, [_P, C.POINTER(Grid), _P, _P, _P, _I, C.POINTER(
 _sig("tr_star_luminosity_split", _I, [_P, _I, _P, _P, _P, C.c_double, C.c_double, C.c_double, _P, _P])
 _sig("tr_uv_rad_pressure", _I, [_P, C.c_int64, _P, _P, _P, _P, C.POINTER(UvParams), _P, _P])
 _sig("tr_dust_equilibrium", _I, [_P, C.c_int64, _P, _P, _P, C.POINTER(DustParams), _P, _P, _P])
+_sig("tr_dust_equilibrium_noalloc", _I, [_P, C.c_int64, _P, _P, _P, C.POINTER(DustParams), _P, _P, _P])
 _sig("tr_mlp_n_params", _I, [])
 _sig("tr_mlp_create", _I, [_P, _P, _P, C.POINTER(_P)])
 _sig("tr_mlp_free", None, [_P])
@@ -356,6 +357,16 @@ def dust_equilibrium(ctx: Context, rho, u_rad, t_gas, p: DustParams, t_dust, ite
     n = int(rho.numel())
     ctx.check(_lib.tr_dust_equilibrium(ctx.h, n, _ptr(rho), _ptr(u_rad), _ptr(t_gas), C.byref(p),
                                        None if mlp is None else mlp.h, _ptr(t_dust), _ptr(iters)))
+
+
+NOALLOC_DUST_STATES = 1 << 22   # TR_NOALLOC_DUST_STATES
+
+
+def dust_equilibrium_noalloc(ctx: Context, rho, u_rad, t_gas, p: DustParams, t_dust, iters=None, mlp=None):
+    """tr_dust_equilibrium_noalloc (no device allocation; at most NOALLOC_DUST_STATES states)."""
+    n = int(rho.numel())
+    ctx.check(_lib.tr_dust_equilibrium_noalloc(ctx.h, n, _ptr(rho), _ptr(u_rad), _ptr(t_gas), C.byref(p),
+                                               None if mlp is None else mlp.h, _ptr(t_dust), _ptr(iters)))
 
 
 class Mlp:

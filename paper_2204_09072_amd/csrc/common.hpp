@@ -38,6 +38,9 @@ struct tr_ctx {
     std::map<std::pair<int, int>, RayTable> tables;
     // pinned host word for reading back the error flag
     int *h_err = nullptr;
+    // this device's scratch of the allocation-free dust solve (TR_NOALLOC_DUST_STATES
+    // floats, shared by every context on the device; never allocated or freed by a call)
+    float *noalloc_guess = nullptr;
     // grow-only workspace for the dust solve's learned starting points
     float *ws_guess = nullptr;
     int64_t ws_guess_n = 0;

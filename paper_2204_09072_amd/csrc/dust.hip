@@ -151,18 +151,12 @@ __global__ __launch_bounds__(256) void k_dust(DustArgs A) {
 
 } // namespace
 
-extern "C" int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, const float *u_rad,
-                                   const float *t_gas, const tr_dust_params *p, const tr_mlp *mlp,
-                                   float *t_dust, uint8_t *iters) {
-    if (!ctx) return TR_EINVAL;
-    if (n < 0 || (n > 0 && (!rho || !u_rad || !t_gas || !t_dust)) || !p)
-        return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad argument");
-    if (!(p->sigma > 0) || !(p->c > 0) || p->c_gd < 0 || p->xi <= 0)
-        return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad constants");
-    if (p->start < 0 || p->start > 2 || p->linear < 0 || p->linear > 1)
-        return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium: bad start (%d) or linear (%d)", p->start, p->linear);
-    if (n == 0) return TR_OK;
-    TR_HIP(ctx, hipSetDevice(ctx->device));
+namespace {
+
+// Checks, then the solve's kernels; `guess` receives the network's starting points (n floats,
+// used only with a network).
+int dust_solve(tr_ctx *ctx, int64_t n, const float *rho, const float *u_rad, const float *t_gas,
+               const tr_dust_params *p, const tr_mlp *mlp, float *t_dust, uint8_t *iters, float *guess) {
     DustArgs A;
     A.n = n; A.rho = rho; A.u_rad = u_rad; A.t_gas = t_gas; A.t_dust = t_dust; A.iters = iters;
     A.a4s = (float)(p->xi * 4.0 * p->sigma);
@@ -175,17 +169,9 @@ extern "C" int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, con
     const int blocks = (int)tr_div_up(n, 256);
     A.guess = nullptr;
     if (mlp) {
-        if (ctx->ws_guess_n < n) {
-            hipFree(ctx->ws_guess);
-            ctx->ws_guess = nullptr;
-            ctx->ws_guess_n = 0;
-            if (hipMalloc(&ctx->ws_guess, sizeof(float) * n) != hipSuccess)
-                return tr_fail(ctx, TR_ENOMEM, "guess workspace");
-            ctx->ws_guess_n = n;
-        }
-        int rc = mlp_guess(ctx, mlp, n, rho, u_rad, t_gas, ctx->ws_guess);
+        int rc = mlp_guess(ctx, mlp, n, rho, u_rad, t_gas, guess);
         if (rc) return rc;
-        A.guess = ctx->ws_guess;
+        A.guess = guess;
         if (p->linear) k_dust<START_LEARNED, false><<<blocks, 256, 0, ctx->stream>>>(A);
         else k_dust<START_LEARNED, true><<<blocks, 256, 0, ctx->stream>>>(A);
     } else if (p->start == 2) {
@@ -199,4 +185,49 @@ extern "C" int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, con
     }
     if (hipGetLastError() != hipSuccess) return tr_fail(ctx, TR_EHIP, "dust kernel launch failed");
     return TR_OK;
+}
+
+int dust_check(tr_ctx *ctx, const char *who, int64_t n, const float *rho, const float *u_rad,
+               const float *t_gas, const tr_dust_params *p, float *t_dust) {
+    if (n < 0 || (n > 0 && (!rho || !u_rad || !t_gas || !t_dust)) || !p)
+        return tr_fail(ctx, TR_EINVAL, "%s: bad argument", who);
+    if (!(p->sigma > 0) || !(p->c > 0) || p->c_gd < 0 || p->xi <= 0)
+        return tr_fail(ctx, TR_EINVAL, "%s: bad constants", who);
+    if (p->start < 0 || p->start > 2 || p->linear < 0 || p->linear > 1)
+        return tr_fail(ctx, TR_EINVAL, "%s: bad start (%d) or linear (%d)", who, p->start, p->linear);
+    return TR_OK;
+}
+
+} // namespace
+
+extern "C" int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, const float *u_rad,
+                                   const float *t_gas, const tr_dust_params *p, const tr_mlp *mlp,
+                                   float *t_dust, uint8_t *iters) {
+    if (!ctx) return TR_EINVAL;
+    int rc = dust_check(ctx, "tr_dust_equilibrium", n, rho, u_rad, t_gas, p, t_dust);
+    if (rc || n == 0) return rc;
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    if (mlp && ctx->ws_guess_n < n) {
+        hipFree(ctx->ws_guess);
+        ctx->ws_guess = nullptr;
+        ctx->ws_guess_n = 0;
+        if (hipMalloc(&ctx->ws_guess, sizeof(float) * n) != hipSuccess)
+            return tr_fail(ctx, TR_ENOMEM, "guess workspace");
+        ctx->ws_guess_n = n;
+    }
+    return dust_solve(ctx, n, rho, u_rad, t_gas, p, mlp, t_dust, iters, ctx->ws_guess);
+}
+
+extern "C" int tr_dust_equilibrium_noalloc(tr_ctx *ctx, int64_t n, const float *rho, const float *u_rad,
+                                           const float *t_gas, const tr_dust_params *p, const tr_mlp *mlp,
+                                           float *t_dust, uint8_t *iters) {
+    if (!ctx) return TR_EINVAL;
+    int rc = dust_check(ctx, "tr_dust_equilibrium_noalloc", n, rho, u_rad, t_gas, p, t_dust);
+    if (rc || n == 0) return rc;
+    if (n > TR_NOALLOC_DUST_STATES)
+        return tr_fail(ctx, TR_EINVAL, "tr_dust_equilibrium_noalloc: %lld states, at most %d",
+                       (long long)n, TR_NOALLOC_DUST_STATES);
+    if (!ctx->noalloc_guess) return tr_fail(ctx, TR_EHIP, "tr_dust_equilibrium_noalloc: no scratch on this device");
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    return dust_solve(ctx, n, rho, u_rad, t_gas, p, mlp, t_dust, iters, ctx->noalloc_guess);
 }

@@ -1,5 +1,33 @@
 // Context lifecycle, errors and synchronisation.
+#include <mutex>
+
 #include "common.hpp"
+
+namespace {
+
+// Scratch of the allocation-free dust solve (tr_dust_equilibrium_noalloc): the guess
+// network's starting temperature of every state, TR_NOALLOC_DUST_STATES floats (16 MiB).
+// Each GPU the library runs on holds its own copy until the process ends.  Host code never
+// uses this name as an address: the per-device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) float scratch[TR_NOALLOC_DUST_STATES];
+
+std::mutex g_scratch_mu;
+std::map<int, float *> g_scratch; // device -> address of that device's scratch
+
+// the calling thread's current device is `device`
+int lookup_scratch(int device, float **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(device);
+    if (it == g_scratch.end()) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TR_EHIP;
+        it = g_scratch.emplace(device, static_cast<float *>(ptr)).first;
+    }
+    *out = it->second;
+    return TR_OK;
+}
+
+} // namespace
 
 int tr_fail(tr_ctx *ctx, int code, const char *fmt, ...) {
     if (ctx) {
@@ -25,6 +53,8 @@ extern "C" int tr_ctx_create(tr_ctx **out, int device, void *stream) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return TR_EHIP; }
     c->n_cu = prop.multiProcessorCount;
+    // once per device, with the device current: the address of its allocation-free scratch
+    if (lookup_scratch(device, &c->noalloc_guess) != TR_OK) { delete c; return TR_EHIP; }
     if (hipMalloc(&c->d_ctl, 64 * sizeof(int)) != hipSuccess) { delete c; return TR_ENOMEM; }
     if (hipMemset(c->d_ctl, 0, 64 * sizeof(int)) != hipSuccess) { hipFree(c->d_ctl); delete c; return TR_EHIP; }
     if (hipHostMalloc(&c->h_err, sizeof(int)) != hipSuccess) { hipFree(c->d_ctl); delete c; return TR_ENOMEM; }
