@@ -6,10 +6,14 @@ tree build (b-nodes, h-nodes, centres of luminosity) -> ray tracing (walk, mappi
 integration, finalisation, u_rad) -> radiation-pressure force -> dust equilibrium with
 the learned Newton guess.  Prints one JSON line.
 
-Default workload: the 128^3 collapsing core (150 Msun in (0.4 pc)^3, rho ~ r^-2 times a
-sigma = 1 lognormal field, T_gas log-uniform 10-300 K), N_side = 4 (192 rays),
-opening angle 1/8.  The guess network is trained before timing on another realisation
-of the same cloud (seed 1), on the GPU, with labels from the library's bracketed solve.
+Default workload: the AMR cloud, 256^3-equivalent (64^3 base grid of 8^3 blocks refined
+twice on density, ~2.5 M leaf cells, 10 stars, T_gas log-uniform 10-300 K), N_side = 4
+(192 rays), opening angle 1/8: the full pipeline.  The guess network is trained before
+timing, on the GPU by the library's own kernels, on 10^6 states: cells of another
+realisation of the cloud (seed 1) traced by the library, plus 20 % log-uniform states,
+labelled with the FP64 oracle's bracketed equilibrium solve (the oracle leg, which also
+times the oracle for `cpu_baseline`).  The same line carries `batch_c4`: the batch of 64
+uneven instances in one autotuned, graph-replayed persistent launch.
 """
 from __future__ import annotations
 
@@ -37,6 +41,7 @@ WORKLOADS = {
 }
 
 B_LEAF, B_HNODE = 12, 36   # algorithmic bytes per accepted b-node / visited h-node
+B_ALPHA = 8                # angular-kernel entry per accepted node (up to 4 (ray, alpha) pairs)
 
 
 def log(*a):
@@ -63,32 +68,43 @@ def make_workload(name, seed=0):
     raise SystemExit(f"unknown workload {name}")
 
 
-def train_network(T, ctx, name, steps):
-    """Guess network trained on another realisation of the workload (untimed setup)."""
-    import torch
-    from paper_2204_09072_amd.guess import train_guess
-    from paper_2204_09072_amd.run import dust, trace, upload
+def training_states(ctx, name, n_total=1_000_000, aug_frac=0.2, seed=1):
+    """(rho, u_rad, T_gas) host arrays for the guess network: random cells of another
+    realisation of the workload, their u_rad traced by the library, plus log-uniform states
+    over the same ranges (untimed setup)."""
     import workloads as W
-    w = make_workload(name, seed=1)
+    from paper_2204_09072_amd.run import trace, upload
+    w = make_workload(name, seed=seed)
     dev = upload(w)
     tree, J, F, U = trace(ctx, w, dev)
     ctx.sync()
-    rho = dev["rho"]
-    tg = dev["t_gas"]
-    # 20 % log-uniform augmentation over the same ranges
-    n_aug = w.n_cells // 4
-    aug = W.dust_samples(n_aug, seed=7, rho_range=(float(w.rho.min()), float(w.rho.max())),
-                         u_range=(max(float(U.min()), 1e-30), float(U.max())),
-                         t_range=(10.0, 300.0)).astype(np.float32)
-    r_all = torch.cat([rho, torch.from_numpy(aug[:, 0]).cuda()])
-    u_all = torch.cat([U, torch.from_numpy(aug[:, 1]).cuda()])
-    t_all = torch.cat([tg, torch.from_numpy(aug[:, 2]).cuda()])
-    Td, _ = dust(ctx, r_all, u_all, t_all, w.units[0], w.units[1])
-    ctx.sync()
+    u = U.cpu().numpy()
     tree.free()
-    mlp, losses = train_guess(ctx, r_all.cpu().numpy(), u_all.cpu().numpy(), t_all.cpu().numpy(),
-                              Td.cpu().numpy(), steps=steps, log_every=max(steps // 5, 1))
-    return mlp, losses
+    n_aug = int(n_total * aug_frac)
+    pick = np.random.default_rng(seed).choice(w.n_cells, min(w.n_cells, n_total - n_aug), replace=False)
+    aug = W.dust_samples(n_aug, seed=7, rho_range=(float(w.rho.min()), float(w.rho.max())),
+                         u_range=(max(float(u.min()), 1e-30), float(u.max())),
+                         t_range=(10.0, 300.0)).astype(np.float32)
+    return (np.concatenate([w.rho[pick], aug[:, 0]]), np.concatenate([u[pick], aug[:, 1]]),
+            np.concatenate([w.t_gas[pick], aug[:, 2]]))
+
+
+def library_labels(T, ctx, states, units):
+    """Labels from the library's own bracketed solve (only when the oracle leg is off)."""
+    import torch
+    from paper_2204_09072_amd.run import dust
+    dv = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in states]
+    Td, _ = dust(ctx, *dv, units[0], units[1])
+    ctx.sync()
+    return Td.cpu().numpy()
+
+
+def train_on(ctx, states, labels, steps):
+    from paper_2204_09072_amd.guess import train_guess
+    t0 = time.perf_counter()
+    mlp, losses = train_guess(ctx, *states, labels, steps=steps, batch=8192, log_every=max(steps // 5, 1))
+    return mlp, {"steps": steps, "samples": int(len(labels)), "seconds": round(time.perf_counter() - t0, 2),
+                 "loss": [round(l, 6) for _, l in losses]}
 
 
 def interior_states(n, seed):
@@ -97,20 +113,6 @@ def interior_states(n, seed):
     import workloads as W
     smp = W.dust_samples(n, seed=seed).astype(np.float32)
     return tuple(torch.from_numpy(np.ascontiguousarray(smp[:, k])).cuda() for k in range(3))
-
-
-def train_interior(T, ctx, units, steps):
-    """Guess network for interior states, trained on a separate draw (untimed setup)."""
-    from paper_2204_09072_amd.guess import train_guess
-    from paper_2204_09072_amd.run import dust
-    r, u, t = interior_states(200_000, seed=31)
-    lab, _ = dust(ctx, r, u, t, units[0], units[1])
-    ctx.sync()
-    t0 = time.perf_counter()
-    mlp, losses = train_guess(ctx, r.cpu().numpy(), u.cpu().numpy(), t.cpu().numpy(), lab.cpu().numpy(),
-                              steps=steps, batch=8192, log_every=max(steps // 5, 1))
-    return mlp, {"steps": steps, "seconds": round(time.perf_counter() - t0, 2),
-                 "loss": [round(l, 6) for _, l in losses]}
 
 
 DUST_VARIANTS = (("learned", True, {}), ("learned_linear_newton", True, dict(linear=True)),
@@ -164,8 +166,18 @@ def dust_summary(stats):
                          "evaluated tries that end once"}
 
 
-def cpu_baseline(w, n_pix, stride, u_rad=None, gpu_t_dust=None):
-    """FP64 oracle on the host cores: tree, every `stride`-th target, force and dust."""
+def oracle_labels(states, units, c_gd=3.8e-33):
+    """The oracle leg's first part: FP64 bracketed equilibrium temperatures of the guess
+    network's training states (host arrays)."""
+    import oracle
+    T, _ = oracle.dust_eq(*[np.asarray(a, np.float64) for a in states], units[0], units[1], c_gd)
+    return T.astype(np.float32)
+
+
+def cpu_baseline(w, n_pix, stride, u_rad=None, gpu_t_dust=None, gpu_counts=None):
+    """FP64 oracle on the host cores: tree, every `stride`-th target, force and dust.  With
+    the GPU's walk counters (int [n_cells, 3]) also checks that the oracle's walk of every
+    traced target accepts and opens the same numbers of nodes."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
@@ -173,8 +185,15 @@ def cpu_baseline(w, n_pix, stride, u_rad=None, gpu_t_dust=None):
     t_tree = time.perf_counter() - t0
     cells = np.arange(0, w.n_cells, stride, dtype=np.int64)
     t0 = time.perf_counter()
-    J, F = ot.trace(oracle.params(w.n_side, theta=w.theta), cells=cells, n_threads=threads)
+    J, F, ocnt = ot.trace(oracle.params(w.n_side, theta=w.theta), cells=cells, n_threads=threads,
+                          counters=True)
     t_trace = time.perf_counter() - t0
+    walk_check = None
+    if gpu_counts is not None:
+        same = np.array_equal(np.asarray(gpu_counts)[cells].astype(np.int64), ocnt)
+        walk_check = {"targets": int(len(cells)), "equal": bool(same)}
+        if not same:
+            raise SystemExit("walk counters of the GPU differ from the oracle's")
     t_dust = 0.0
     errs = None
     if w.cgs and w.t_gas is not None:
@@ -210,6 +229,8 @@ def cpu_baseline(w, n_pix, stride, u_rad=None, gpu_t_dust=None):
                    f"estimated step {t_step1:.1f} s")}
     if errs:
         out["dust_max_rel_err"] = errs
+    if walk_check:
+        out["walk_counts_vs_oracle"] = walk_check
     return out
 
 
@@ -318,6 +339,33 @@ def traffic_probe(name):
     log(f"traffic probe {name}: one trace launch done")
 
 
+def mlp_probe(n=2_097_152, steps=20, reps=3):
+    """Guess-network inference (k_mlp_infer) followed by the learned-start solve on n
+    log-uniform interior states, `reps` times, then `steps` training steps of 8192 samples
+    (k_mlp_train + k_adam): for rocprofv3 runs of the matrix-core counters."""
+    import torch
+    import paper_2204_09072_amd as T
+    import workloads as W
+    from paper_2204_09072_amd.guess import features
+    ctx = T.Context(0)
+    r, u, t = interior_states(n, seed=32)
+    f = features(*(x.cpu().numpy().astype(np.float64) for x in (r, u, t)))
+    norm = np.array([*f.mean(0), *(1.0 / f.std(0)), 1.3, 2.0], np.float32)
+    mlp = T.Mlp(ctx, T.init_mlp_params(0), norm)
+    out = torch.empty(n, device="cuda")
+    dp = T.dust_params(W.SIGMA_SB, W.C_LIGHT)
+    for _ in range(reps):
+        T.dust_equilibrium(ctx, r, u, t, dp, out, None, mlp)
+    rng = np.random.default_rng(5)
+    x = torch.from_numpy(rng.normal(size=(8192, 3)).astype(np.float32)).cuda()
+    y = torch.from_numpy(rng.normal(size=8192).astype(np.float32)).cuda()
+    for _ in range(steps):
+        mlp.train_step(x, y, 1e-3)
+    ctx.sync()
+    log(f"mlp probe: {reps} inferences of {n} states, {steps} training steps of 8192")
+    mlp.free()
+
+
 def ray_count_study(name):
     """Cost and accuracy of 48, 192 and 768 rays on one workload (the paper's Sec. 7.6
     comparison): trace time per N_side (opening angle 1/(2 N_side)), cost relative to 48
@@ -372,15 +420,64 @@ def ray_count_study(name):
     tree.free()
 
 
+def batch_c4(T, ctx, reps):
+    """The 64 uneven instances (edges 32-96, N_side 2 or 4, 0-4 stars; 24.1 M cells) in one
+    persistent launch: trees built, the launch autotuned on a sample of targets and captured
+    in a HIP graph, then `reps` graph replays timed with HIP events on the library's stream."""
+    import torch
+    import workloads as W
+    from paper_2204_09072_amd.run import params_of, tree_of, upload
+    log("batch of 64 instances ...")
+    t0 = time.perf_counter()
+    ws = W.c4_batch64()
+    trees, J, F = [], [], []
+    for w in ws:
+        trees.append(tree_of(ctx, w, upload(w)))
+        J.append(torch.empty(w.n_cells, device="cuda"))
+        F.append(torch.empty((3, w.n_cells), device="cuda"))
+    ctx.sync()
+    b = T.Batch(ctx, trees, [params_of(w) for w in ws], J, F, None)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tun = b.tune(sample_stride=16)
+    t_tune = time.perf_counter() - t0
+    b.launch()                      # warm-up replay
+    ctx.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ms = e0.elapsed_time(e1) / reps
+    cells = sum(w.n_cells for w in ws)
+    rays = sum(w.n_cells * 12 * w.n_side ** 2 for w in ws)
+    b.free()
+    for t in trees:
+        t.free()
+    return {"value": rays / (ms / 1000.0), "unit": "target-ray evaluations/s", "ms_per_launch": round(ms, 2),
+            "replays": reps, "instances": len(ws), "cells": int(cells), "target_rays": int(rays),
+            "tuned": {"bins_per_pass": tun.bins_per_pass, "waves_per_block": tun.waves_per_block,
+                      "chunk": tun.chunk, "sample_ms": round(tun.sample_ms, 3), "tune_seconds": round(t_tune, 2)},
+            "setup_seconds": round(t_setup, 2),
+            "workload": "64 instances, edge uniform over {32, 40, ..., 96} (8^3 blocks), lognormal sigma=1.5, "
+                        "kappa 0.1-10, 0-4 stars of L=1, N_side 2 or 4, code units; one autotuned persistent "
+                        "launch replayed from a HIP graph"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="core128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="amr256", choices=sorted(WORKLOADS))
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--cpu-stride", type=int, default=128)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (timing, training labels and walk-count check)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch (batch_c4)")
+    ap.add_argument("--batch-reps", type=int, default=2)
     ap.add_argument("--bins-per-pass", type=int, default=0)
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
@@ -395,6 +492,8 @@ def main():
     ap.add_argument("--traffic-out", nargs="*", default=None)
     ap.add_argument("--tcc", nargs="*", default=None, metavar="DIR",
                     help="with --write-traffic: a TCC_HIT_sum TCC_MISS_sum run for the L2 hit rate")
+    ap.add_argument("--mlp-probe", action="store_true",
+                    help="guess-network inference and training only, for rocprofv3 --pmc runs")
     ap.add_argument("--ray-study", action="store_true",
                     help="trace cost and T_J accuracy at 48, 192 and 768 rays (prints one JSON line)")
     args = ap.parse_args()
@@ -427,6 +526,9 @@ def main():
     if args.ray_study:
         ray_count_study(args.workload)
         return
+    if args.mlp_probe:
+        mlp_probe()
+        return
 
     import torch
     import paper_2204_09072_amd as T
@@ -437,14 +539,20 @@ def main():
     ctx = T.Context(0)
     dev = upload(w)
     log(f"workload {args.workload}: {w.n_cells} cells, {n_pix} rays")
+    oracle_leg = not args.no_cpu_baseline
 
+    # guess network (untimed setup): trained by the library on 10^6 states labelled by the
+    # oracle leg's FP64 equilibrium solve (the library's own solve when that leg is off)
     mlp = None
     train_info = None
     if w.cgs:
+        states = training_states(ctx, args.workload)
         t0 = time.perf_counter()
-        mlp, losses = train_network(T, ctx, args.workload, args.train_steps)
-        train_info = {"steps": args.train_steps, "seconds": round(time.perf_counter() - t0, 2),
-                      "loss": [round(l, 6) for _, l in losses]}
+        labels = oracle_labels(states, w.units) if oracle_leg else library_labels(T, ctx, states, w.units)
+        t_lab = time.perf_counter() - t0
+        mlp, train_info = train_on(ctx, states, labels, args.train_steps)
+        train_info["labels"] = ("FP64 oracle, bracketed solve (%.2f s)" % t_lab) if oracle_leg else \
+            "library's bracketed solve (oracle leg off)"
         log("guess network trained", train_info)
 
     p = params_of(w, bins_per_pass=args.bins_per_pass, waves_per_block=args.waves_per_block,
@@ -501,13 +609,18 @@ def main():
     tree = trees[-1]
     ms = (t1 - t0) * 1000.0 / args.steps
     value = n * n_pix / (ms / 1000.0)
+    log(f"timed {args.steps} steps: {ms:.1f} ms per step")
 
-    # roofline of the dominant kernel (the ray-tracing walk)
+    # roofline of the dominant kernel (the ray-tracing walk): algorithmic bytes from the walk
+    # counters (checked against the oracle's on the oracle leg's targets)
     cnt = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
     T.walk_counts(ctx, tree, params_of(w), cnt)
     ctx.sync()
-    c = cnt.to(torch.int64).sum(0).cpu().numpy()
-    alg_bytes = float(B_LEAF * c[0] + B_HNODE * (c[1] + c[2]))
+    cnt_h = cnt.cpu().numpy()
+    c = cnt_h.astype(np.int64).sum(0)
+    node_bytes = float(B_LEAF * c[0] + B_HNODE * (c[1] + c[2]))
+    alpha_bytes = float(B_ALPHA * (c[0] + c[1]))
+    alg_bytes = node_bytes + alpha_bytes
     t_trace = float(np.mean(times["trace"])) / 1000.0
     achieved = alg_bytes / t_trace / 1e9
     traffic = l2_hit = None
@@ -522,6 +635,10 @@ def main():
             "frac": round(achieved / 8000.0, 4), "traffic": traffic,
             "l2_hit_rate": None if l2_hit is None else round(l2_hit, 4),
             "kernel": "k_trace", "algorithmic_bytes_per_launch": alg_bytes,
+            "algorithmic_bytes": ("12 B per accepted leaf + 36 B per accepted or opened h-node (node "
+                                  "records) + 8 B per accepted node (its angular-kernel entry of up to "
+                                  "4 (ray, alpha) pairs)"),
+            "node_bytes_per_launch": node_bytes, "alpha_bytes_per_launch": alpha_bytes,
             "kernel_ms": round(t_trace * 1000, 3),
             "walk_totals": {"b_nodes_accepted": int(c[0]), "h_nodes_accepted": int(c[1]),
                             "h_nodes_opened": int(c[2])}}
@@ -536,10 +653,13 @@ def main():
         dust = dust_summary(stats)
         dust["network"] = train_info
         # states inside the bracket (log-uniform over the dense-cloud range), where a guess
-        # can help: in the core most cells have T_dust at a bracket end (T_gas or T_J)
+        # can help: in the cloud most cells have T_dust at a bracket end (T_gas or T_J)
         log("dust on interior states ...")
         t0 = time.perf_counter()
-        mlp_i, info_i = train_interior(T, ctx, w.units, args.train_steps)
+        st_tr = interior_states(200_000, seed=31)
+        st_tr = tuple(x.cpu().numpy() for x in st_tr)
+        lab = oracle_labels(st_tr, w.units) if oracle_leg else library_labels(T, ctx, st_tr, w.units)
+        mlp_i, info_i = train_on(ctx, st_tr, lab, args.train_steps)
         ri, ui, ti = interior_states(n, seed=32)
         st_i, _ = dust_compare(T, ctx, mlp_i, ri, ui, ti, w.units)
         dust["interior_states"] = dict(dust_summary(st_i), network=info_i,
@@ -549,10 +669,12 @@ def main():
                                        seconds=round(time.perf_counter() - t0, 2))
         mlp_i.free()
 
+    batch = None if args.no_batch else batch_c4(T, ctx, args.batch_reps)
+
     base = None
-    if not args.no_cpu_baseline:
+    if oracle_leg:
         log("cpu baseline (oracle) ...")
-        base = cpu_baseline(w, n_pix, args.cpu_stride, U.cpu().numpy(), dust_T)
+        base = cpu_baseline(w, n_pix, args.cpu_stride, U.cpu().numpy(), dust_T, gpu_counts=cnt_h)
         if dust is not None and base.get("dust_max_rel_err"):
             for k, v in base.pop("dust_max_rel_err").items():
                 dust["variants"][k]["max_rel_err_vs_oracle"] = v
@@ -576,6 +698,7 @@ def main():
         "kernels_ms": {k: round(float(np.mean(v)), 3) for k, v in times.items() if v},
         "dust": dust,
         "roofline": roof,
+        "batch_c4": batch,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)
