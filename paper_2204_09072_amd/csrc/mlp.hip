@@ -30,6 +30,7 @@ namespace {
 
 constexpr int H = MLP_H;
 constexpr int S = 32;          // samples per wave step
+constexpr int64_t kMaxInfer = (int64_t)1 << 28; // inference: byte offsets of [n][3] inputs fit 32 bits
 constexpr int LD = H + 4;      // padded row of a bfloat16 tile
 
 __device__ __forceinline__ uint16_t bf16_bits(float x) {
@@ -279,20 +280,33 @@ __device__ __forceinline__ bf8v bf8_of(uint32_t a, uint32_t b, uint32_t c, uint3
 }
 // max(x, 0) in one integer max: negative floats have negative bit patterns
 __device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
-// eight accumulators v0 .. v0 + 7 of a tile, ReLU'd and packed as a K = 16 operand
+// ReLU of two packed bfloat16 values in one packed 16-bit integer max: a negative value
+// (its sign bit set) is a negative int16, and rounding to bfloat16 keeps the sign, so
+// max(round(x), 0) = round(max(x, 0))
+typedef short sh2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
+    const sh2 x = __builtin_bit_cast(sh2, v);
+    const sh2 z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, z));
+}
+// eight accumulators v0 .. v0 + 7 of a tile, rounded to bfloat16, ReLU'd, packed as a
+// K = 16 operand
 __device__ __forceinline__ bf8v relu_pack8(const f16v &a, int v0) {
-    return bf8_of(pk_bf16(relu(a[v0]), relu(a[v0 + 1])), pk_bf16(relu(a[v0 + 2]), relu(a[v0 + 3])),
-                  pk_bf16(relu(a[v0 + 4]), relu(a[v0 + 5])), pk_bf16(relu(a[v0 + 6]), relu(a[v0 + 7])));
+    return bf8_of(relu_bf16x2(pk_bf16(a[v0], a[v0 + 1])), relu_bf16x2(pk_bf16(a[v0 + 2], a[v0 + 3])),
+                  relu_bf16x2(pk_bf16(a[v0 + 4], a[v0 + 5])), relu_bf16x2(pk_bf16(a[v0 + 6], a[v0 + 7])));
 }
 
 // Inference, 32 samples per wave step, all operands in registers (layouts in the header).
 // The second product runs on v_mfma_f32_32x32x16_bf16 (K = 16 per instruction): lane l
 // contributes 8 K-slots, A and B slot for slot, and a contraction may visit K in any
 // order, so K-block kk takes accumulators v = 8 (kk % 2) + j of first-layer tile kk / 2 as
-// its B slots and the matching columns of W2 as its A slots.  The next step's inputs are
-// loaded while the current step computes.  The output layer is a third product,
-// y[s] = sum_k w3[k] h2[k][s], with w3 as row 0 of its A operand and h2 packed exactly as
-// h1 was; row 0 of the result is accumulator 0 of lanes 0..31.
+// its B slots and the matching columns of W2 as its A slots.  Its bias enters as the
+// accumulators' starting value (accumulator v of lane l is hidden unit 32 t + 8 (v / 4) +
+// 4 half + v % 4).  The next step's inputs are loaded while the current step computes.
+// The output layer is a third product, y[s] = sum_k w3[k] h2[k][s], with w3 as row 0 of
+// its A operand and h2 packed exactly as h1 was; row 0 of the result is accumulator 0 of
+// lanes 0..31.  Logarithm and exponential are the hardware's base-2 instructions (about
+// 1 ulp, far finer than the bfloat16 rounding of the inputs and the solve's tolerance).
 template <int MODE>
 __global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs A) {
     const int lane = threadIdx.x & 63, col = lane & 31, half = lane >> 5;
@@ -300,23 +314,26 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs A) {
     const int nwave = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
     const float *W1 = A.p, *B1 = A.p + MLP_OFF_B1, *W2 = A.p + MLP_OFF_W2, *B2 = A.p + MLP_OFF_B2,
                 *W3 = A.p + MLP_OFF_W3;
-    // weights as operands: [W1 | b1] and [b2] (half-wave 0 holds k = 0..3, half-wave 1 the
-    // zero padding), W2 rows 32 t + col, and w3 in row 0 (lanes 0 and 32) with the same
-    // slot order as W2's columns
-    sh4 aw1[2], ab2[2];
+    // weights as operands: [W1 | b1] (half-wave 0 holds k = 0..3, half-wave 1 the zero
+    // padding), W2 rows 32 t + col, and w3 in row 0 (lanes 0 and 32) with the same slot
+    // order as W2's columns; b2 (rounded to bfloat16, as the network's parameters are) as the
+    // second product's starting accumulators
+    sh4 aw1[2];
     bf8v aw2[2][H / 16], aw3[H / 16];
+    f16v c2[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int n = 32 * t + col;
         aw1[t] = half == 0 ? sh4_of(pk_bf16(W1[3 * n], W1[3 * n + 1]), pk_bf16(W1[3 * n + 2], B1[n]))
                            : sh4_of(0u, 0u);
-        ab2[t] = half == 0 ? sh4_of(pk_bf16(B2[n], 0.0f), 0u) : sh4_of(0u, 0u);
 #pragma unroll
         for (int kk = 0; kk < H / 16; ++kk) {
             // slot j <-> hidden unit 32 (kk / 2) + 16 (kk % 2) + 8 (j / 4) + 4 half + j % 4
             const float *w = W2 + H * n + 32 * (kk >> 1) + 16 * (kk & 1) + 4 * half;
             aw2[t][kk] = bf8_of(pk_bf16(w[0], w[1]), pk_bf16(w[2], w[3]), pk_bf16(w[8], w[9]), pk_bf16(w[10], w[11]));
         }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) c2[t][v] = bf16_val(bf16_bits(B2[32 * t + 8 * (v >> 2) + 4 * half + (v & 3)]));
     }
 #pragma unroll
     for (int kk = 0; kk < H / 16; ++kk) {
@@ -325,33 +342,42 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs A) {
                            : bf8_of(0u, 0u, 0u, 0u);
     }
     const float b3 = bf16_val(bf16_bits(A.p[MLP_OFF_B3]));
-    const sh4 bone = half == 0 ? sh4_of(pk_bf16(1.0f, 0.0f), 0u) : sh4_of(0u, 0u);
+    const float inv_out = 1.0f / A.out_scale;
     const f16v zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    constexpr float kLog10of2 = 0.30102999566398120f, kLog2of10 = 3.32192809488736235f;
     const int64_t nchunk = (A.n + S - 1) / S;
-    // raw inputs of sample ch * 32 + col (half-wave 0 only)
+    // Inputs and outputs go through buffer descriptors, whose range check returns 0 for a
+    // load and drops a store at an offset beyond the array: every lane issues every load
+    // and store (lanes without a sample at an out-of-range offset), so no memory operation
+    // sits under a lane mask and a step waits only for the loads it reads.
+    constexpr uint32_t kOut = 0xfffffff0u; // beyond any array (n < 2^28)
+    const uint32_t nb = (uint32_t)A.n * 4u;
+    const __amdgpu_buffer_rsrc_t rin0 = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(MODE == GUESS ? A.rho : A.x), (short)0, (int)(MODE == GUESS ? nb : 3u * nb), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rin1 =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(MODE == GUESS ? A.u_rad : A.x), (short)0, (int)(MODE == GUESS ? nb : 3u * nb), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rin2 =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(MODE == GUESS ? A.t_gas : A.x), (short)0, (int)(MODE == GUESS ? nb : 3u * nb), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc((void *)A.out, (short)0, (int)nb, 0x00020000);
+    // raw inputs of sample ch * 32 + col (half-wave 0 only; 0 elsewhere)
     auto load = [&](int64_t ch, float &x0, float &x1, float &x2) {
         const int64_t s = ch * S + col;
-        x0 = x1 = x2 = 1.0f;
-        if (half == 0 && ch < nchunk && s < A.n) {
-            if (MODE == GUESS) {
-                x0 = A.rho[s]; x1 = A.u_rad[s]; x2 = A.t_gas[s];
-            } else {
-                x0 = A.x[3 * s]; x1 = A.x[3 * s + 1]; x2 = A.x[3 * s + 2];
-            }
-        }
+        const bool own = half == 0 && s < A.n;
+        const uint32_t o = own ? (uint32_t)s * (MODE == GUESS ? 4u : 12u) : kOut;
+        x0 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rin0, o, 0, 0));
+        x1 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rin1, MODE == GUESS ? o : o + 4u, 0, 0));
+        x2 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rin2, MODE == GUESS ? o : o + 8u, 0, 0));
     };
-    float r0, r1, r2;
-    load(wave, r0, r1, r2);
-    for (int64_t ch = wave; ch < nchunk; ch += nwave) {
+    // log10 of an input clamped to 1e-37 (a normal float, as v_log_f32 requires)
+    auto lg10 = [&](float x) { return __builtin_amdgcn_logf(fmaxf(x, 1e-37f)) * kLog10of2; };
+    // one 32-sample step on inputs already in registers
+    auto step = [&](int64_t ch, float x0, float x1, float x2) {
         const int64_t s = ch * S + col;
         const bool live = half == 0 && s < A.n;
-        float x0 = r0, x1 = r1, x2 = r2;
-        load(ch + nwave, r0, r1, r2);
         if (MODE == GUESS) {
-            // hardware logarithm (about 1 ulp): far finer than the inputs' bfloat16 rounding
-            x0 = (__log10f(fmaxf(x0, 1e-37f)) - A.shift[0]) * A.scale[0];
-            x1 = (__log10f(fmaxf(x1, 1e-37f)) - A.shift[1]) * A.scale[1];
-            x2 = (__log10f(fmaxf(x2, 1e-37f)) - A.shift[2]) * A.scale[2];
+            x0 = (lg10(x0) - A.shift[0]) * A.scale[0];
+            x1 = (lg10(x1) - A.shift[1]) * A.scale[1];
+            x2 = (lg10(x2) - A.shift[2]) * A.scale[2];
         }
         // B operand of the first product: column s = (x0, x1, x2, 1) in half-wave 0
         const sh4 bx = live ? sh4_of(pk_bf16(x0, x1), pk_bf16(x2, 1.0f)) : sh4_of(0u, 0u);
@@ -366,7 +392,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs A) {
         f16v a2[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            a2[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ab2[t], bone, zero, 0, 0, 0);
+            a2[t] = c2[t];
 #pragma unroll
             for (int kk = 0; kk < H / 16; ++kk)
                 a2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw2[t][kk], bh[kk], a2[t], 0, 0, 0);
@@ -375,10 +401,25 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs A) {
 #pragma unroll
         for (int kk = 0; kk < H / 16; ++kk)
             a3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw3[kk], relu_pack8(a2[kk >> 1], 8 * (kk & 1)), a3, 0, 0, 0);
-        if (live) {
-            const float yv = a3[0] + b3;
-            A.out[s] = MODE == GUESS ? __exp10f(yv / A.out_scale + A.out_shift) : yv;
-        }
+        const float yv = a3[0] + b3;
+        const float yo = MODE == GUESS ? __builtin_amdgcn_exp2f((yv * inv_out + A.out_shift) * kLog2of10) : yv;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(yo), rout, live ? (uint32_t)s * 4u : kOut, 0, 0);
+    };
+    // a wave takes steps wave, wave + nwave, ...; the inputs of the next three are in flight
+    // while one computes (three register sets, so no step waits on a load issued just before)
+    float a0, a1, a2, b0, b1, b2, c0, c1, c2_;
+    load(wave, a0, a1, a2);
+    load(wave + nwave, b0, b1, b2);
+    load(wave + 2 * (int64_t)nwave, c0, c1, c2_);
+    for (int64_t ch = wave; ch < nchunk; ch += 3 * (int64_t)nwave) {
+        step(ch, a0, a1, a2);
+        load(ch + 3 * (int64_t)nwave, a0, a1, a2);
+        if (ch + nwave >= nchunk) break; // uniform over the wave
+        step(ch + nwave, b0, b1, b2);
+        load(ch + 4 * (int64_t)nwave, b0, b1, b2);
+        if (ch + 2 * (int64_t)nwave >= nchunk) break;
+        step(ch + 2 * (int64_t)nwave, c0, c1, c2_);
+        load(ch + 5 * (int64_t)nwave, c0, c1, c2_);
     }
 }
 
@@ -434,6 +475,7 @@ MlpArgs base_args(const tr_mlp *m, int64_t n) {
 
 int mlp_guess(tr_ctx *ctx, const tr_mlp *m, int64_t n, const float *rho, const float *u_rad,
               const float *t_gas, float *guess) {
+    if (n >= kMaxInfer) return tr_fail(ctx, TR_EINVAL, "guess network: %lld states, fewer than 2^28 required", (long long)n);
     MlpArgs A = base_args(m, n);
     A.rho = rho; A.u_rad = u_rad; A.t_gas = t_gas; A.out = guess;
     k_mlp_infer<GUESS><<<grid_for(ctx, n, 3), 256, 0, ctx->stream>>>(A); // 3 waves/SIMD fit
@@ -490,6 +532,7 @@ extern "C" int tr_mlp_forward(tr_ctx *ctx, const tr_mlp *m, int64_t n, const flo
     if (!m || n < 0) return tr_fail(ctx, TR_EINVAL, "tr_mlp_forward: bad argument");
     if (n == 0) return TR_OK;
     if (!x || !y) return tr_fail(ctx, TR_EINVAL, "tr_mlp_forward: null buffer");
+    if (n >= kMaxInfer) return tr_fail(ctx, TR_EINVAL, "tr_mlp_forward: %lld samples, fewer than 2^28 required", (long long)n);
     MlpArgs A = base_args(m, n);
     A.x = x; A.out = y;
     k_mlp_infer<FORWARD><<<grid_for(ctx, n, 3), 256, 0, ctx->stream>>>(A);
