@@ -116,6 +116,7 @@ def interior_states(n, seed):
 
 
 DUST_VARIANTS = (("learned", True, {}), ("learned_linear_newton", True, dict(linear=True)),
+                 ("learned_staged", True, dict(staged=True)),
                  ("plain", False, dict(start=1, linear=True, max_iter=250)),
                  ("plain_log_newton", False, dict(start=1)), ("secant_log_newton", False, dict(start=0)),
                  ("plain_bisection", False, dict(start=2, max_iter=250)))

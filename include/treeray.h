@@ -204,19 +204,24 @@ typedef struct tr_dust_params {
                          counts, stopping when the bracket width is <= rel_tol T) */
     int32_t linear;   /* 0 = Newton on ln w(T) against ln T, 1 = Newton on the residual g(T);
                          ignored by bisection */
+    int32_t staged;   /* with a network: 0 = one kernel, the guesses kept in registers;
+                         1 = the network's inference into a buffer, then the solve (the same
+                         guesses and results; the form tr_dust_equilibrium_noalloc takes) */
 } tr_dust_params;
 
 /* rho, u_rad, t_gas: device float[n]; t_dust: device float[n]; iters: device uint8[n]
  * or NULL (Newton/bisection steps taken).  mlp: trained guess network (its output is the
- * starting point) or NULL for the plain start chosen by p->start. */
+ * starting point) or NULL for the plain start chosen by p->start.  With a network n must be
+ * below 2^28. */
 int tr_dust_equilibrium(tr_ctx *ctx, int64_t n, const float *rho, const float *u_rad,
                         const float *t_gas, const tr_dust_params *p, const tr_mlp *mlp,
                         float *t_dust, uint8_t *iters);
 
 /* Allocation-free variant of tr_dust_equilibrium, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
- * hipMalloc).  Same arguments, kernels and results, but the guess network's starting
- * temperatures go to a fixed scratch array of TR_NOALLOC_DUST_STATES floats (16 MiB) that each
+ * hipMalloc).  Same arguments and results; with a network it always takes the staged form
+ * (p->staged is ignored), whose starting temperatures go to a fixed scratch array of
+ * TR_NOALLOC_DUST_STATES floats (16 MiB) that each
  * GPU holds from the library's first context on it until the process ends.  n above
  * TR_NOALLOC_DUST_STATES fails with TR_EINVAL before any work; the call makes no hipMalloc or
  * hipFree.  Every call on one GPU shares that GPU's array: calls that overlap in time on one

@@ -66,7 +66,8 @@ class UvParams(C.Structure):
 
 class DustParams(C.Structure):
     _fields_ = [("sigma", C.c_double), ("c", C.c_double), ("c_gd", C.c_double), ("xi", C.c_double),
-                ("rel_tol", C.c_float), ("max_iter", C.c_int32), ("start", C.c_int32), ("linear", C.c_int32)]
+                ("rel_tol", C.c_float), ("max_iter", C.c_int32), ("start", C.c_int32), ("linear", C.c_int32),
+                ("staged", C.c_int32)]
 
 
 def _sig(name, res, args):
@@ -344,12 +345,14 @@ def rad_force(ctx: Context, tree: Tree, F, a_rp, p_src=None):
     ctx.check(_lib.tr_rad_force(ctx.h, tree.h, _ptr(F), _ptr(a_rp), _ptr(p_src)))
 
 
-def dust_params(sigma, c, c_gd=3.8e-33, xi=1.0, rel_tol=0.0, max_iter=0, start=0, linear=False) -> DustParams:
+def dust_params(sigma, c, c_gd=3.8e-33, xi=1.0, rel_tol=0.0, max_iter=0, start=0, linear=False,
+                staged=False) -> DustParams:
     """start 0: secant point of the bracket (log space); 1: the bracket end nearer the root;
     2: plain bisection (no Newton steps).  linear: Newton on the residual itself instead of
-    on ln w against ln T."""
+    on ln w against ln T.  staged (with a network): the inference into a buffer, then the
+    solve, instead of one kernel."""
     return DustParams(float(sigma), float(c), float(c_gd), float(xi), float(rel_tol), int(max_iter),
-                      int(start), int(bool(linear)))
+                      int(start), int(bool(linear)), int(bool(staged)))
 
 
 def dust_equilibrium(ctx: Context, rho, u_rad, t_gas, p: DustParams, t_dust, iters=None, mlp=None):

@@ -23,8 +23,8 @@
 
 #include "mlp.hpp"
 
-typedef short sh4 __attribute__((ext_vector_type(4)));
-typedef float f16v __attribute__((ext_vector_type(16)));
+using trnet::f16v;
+using trnet::sh4;
 
 namespace {
 
@@ -260,42 +260,6 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpArgs A) {
     if (col == 0) atomicAdd(A.loss, lsum * A.inv_n);
 }
 
-// two floats to packed bfloat16 (round to nearest even, v_cvt_pk_bf16_f32)
-typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
-typedef float f2v __attribute__((ext_vector_type(2)));
-typedef unsigned u2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
-    const f2v x = {a, b};
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf2v));
-}
-__device__ __forceinline__ sh4 sh4_of(uint32_t lo, uint32_t hi) {
-    const u2v v = {lo, hi};
-    return __builtin_bit_cast(sh4, v);
-}
-typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
-typedef unsigned u4v __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ bf8v bf8_of(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
-    const u4v v = {a, b, c, d};
-    return __builtin_bit_cast(bf8v, v);
-}
-// max(x, 0) in one integer max: negative floats have negative bit patterns
-__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
-// ReLU of two packed bfloat16 values in one packed 16-bit integer max: a negative value
-// (its sign bit set) is a negative int16, and rounding to bfloat16 keeps the sign, so
-// max(round(x), 0) = round(max(x, 0))
-typedef short sh2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
-    const sh2 x = __builtin_bit_cast(sh2, v);
-    const sh2 z = {0, 0};
-    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, z));
-}
-// eight accumulators v0 .. v0 + 7 of a tile, rounded to bfloat16, ReLU'd, packed as a
-// K = 16 operand
-__device__ __forceinline__ bf8v relu_pack8(const f16v &a, int v0) {
-    return bf8_of(relu_bf16x2(pk_bf16(a[v0], a[v0 + 1])), relu_bf16x2(pk_bf16(a[v0 + 2], a[v0 + 3])),
-                  relu_bf16x2(pk_bf16(a[v0 + 4], a[v0 + 5])), relu_bf16x2(pk_bf16(a[v0 + 6], a[v0 + 7])));
-}
-
 // Inference, 32 samples per wave step, all operands in registers (layouts in the header).
 // The second product runs on v_mfma_f32_32x32x16_bf16 (K = 16 per instruction): lane l
 // contributes 8 K-slots, A and B slot for slot, and a contraction may visit K in any
@@ -312,39 +276,9 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs A) {
     const int lane = threadIdx.x & 63, col = lane & 31, half = lane >> 5;
     const int wave = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
     const int nwave = (int)((gridDim.x * (int64_t)blockDim.x) >> 6);
-    const float *W1 = A.p, *B1 = A.p + MLP_OFF_B1, *W2 = A.p + MLP_OFF_W2, *B2 = A.p + MLP_OFF_B2,
-                *W3 = A.p + MLP_OFF_W3;
-    // weights as operands: [W1 | b1] (half-wave 0 holds k = 0..3, half-wave 1 the zero
-    // padding), W2 rows 32 t + col, and w3 in row 0 (lanes 0 and 32) with the same slot
-    // order as W2's columns; b2 (rounded to bfloat16, as the network's parameters are) as the
-    // second product's starting accumulators
-    sh4 aw1[2];
-    bf8v aw2[2][H / 16], aw3[H / 16];
-    f16v c2[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int n = 32 * t + col;
-        aw1[t] = half == 0 ? sh4_of(pk_bf16(W1[3 * n], W1[3 * n + 1]), pk_bf16(W1[3 * n + 2], B1[n]))
-                           : sh4_of(0u, 0u);
-#pragma unroll
-        for (int kk = 0; kk < H / 16; ++kk) {
-            // slot j <-> hidden unit 32 (kk / 2) + 16 (kk % 2) + 8 (j / 4) + 4 half + j % 4
-            const float *w = W2 + H * n + 32 * (kk >> 1) + 16 * (kk & 1) + 4 * half;
-            aw2[t][kk] = bf8_of(pk_bf16(w[0], w[1]), pk_bf16(w[2], w[3]), pk_bf16(w[8], w[9]), pk_bf16(w[10], w[11]));
-        }
-#pragma unroll
-        for (int v = 0; v < 16; ++v) c2[t][v] = bf16_val(bf16_bits(B2[32 * t + 8 * (v >> 2) + 4 * half + (v & 3)]));
-    }
-#pragma unroll
-    for (int kk = 0; kk < H / 16; ++kk) {
-        const float *w = W3 + 32 * (kk >> 1) + 16 * (kk & 1) + 4 * half;
-        aw3[kk] = col == 0 ? bf8_of(pk_bf16(w[0], w[1]), pk_bf16(w[2], w[3]), pk_bf16(w[8], w[9]), pk_bf16(w[10], w[11]))
-                           : bf8_of(0u, 0u, 0u, 0u);
-    }
-    const float b3 = bf16_val(bf16_bits(A.p[MLP_OFF_B3]));
+    trnet::Net net;
+    net.load(A.p, col, half);
     const float inv_out = 1.0f / A.out_scale;
-    const f16v zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    constexpr float kLog10of2 = 0.30102999566398120f, kLog2of10 = 3.32192809488736235f;
     const int64_t nchunk = (A.n + S - 1) / S;
     // Inputs and outputs go through buffer descriptors, whose range check returns 0 for a
     // load and drops a store at an offset beyond the array: every lane issues every load
@@ -368,49 +302,27 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs A) {
         x1 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rin1, MODE == GUESS ? o : o + 4u, 0, 0));
         x2 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rin2, MODE == GUESS ? o : o + 8u, 0, 0));
     };
-    // log10 of an input clamped to 1e-37 (a normal float, as v_log_f32 requires)
-    auto lg10 = [&](float x) { return __builtin_amdgcn_logf(fmaxf(x, 1e-37f)) * kLog10of2; };
     // one 32-sample step on inputs already in registers
     auto step = [&](int64_t ch, float x0, float x1, float x2) {
         const int64_t s = ch * S + col;
         const bool live = half == 0 && s < A.n;
         if (MODE == GUESS) {
-            x0 = (lg10(x0) - A.shift[0]) * A.scale[0];
-            x1 = (lg10(x1) - A.shift[1]) * A.scale[1];
-            x2 = (lg10(x2) - A.shift[2]) * A.scale[2];
+            x0 = trnet::feature(x0, A.shift[0], A.scale[0]);
+            x1 = trnet::feature(x1, A.shift[1], A.scale[1]);
+            x2 = trnet::feature(x2, A.shift[2], A.scale[2]);
         }
         // B operand of the first product: column s = (x0, x1, x2, 1) in half-wave 0
-        const sh4 bx = live ? sh4_of(pk_bf16(x0, x1), pk_bf16(x2, 1.0f)) : sh4_of(0u, 0u);
-        f16v a1[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) a1[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aw1[t], bx, zero, 0, 0, 0);
-        // h1 = ReLU(a1) in bfloat16: K-block kk holds accumulators 8 (kk % 2) + 0..7 of
-        // tile kk / 2 (rows 16 (kk % 2) + 8 (j / 4) + 4 half + j % 4)
-        bf8v bh[H / 16];
-#pragma unroll
-        for (int kk = 0; kk < H / 16; ++kk) bh[kk] = relu_pack8(a1[kk >> 1], 8 * (kk & 1));
-        f16v a2[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            a2[t] = c2[t];
-#pragma unroll
-            for (int kk = 0; kk < H / 16; ++kk)
-                a2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw2[t][kk], bh[kk], a2[t], 0, 0, 0);
-        }
-        f16v a3 = zero;
-#pragma unroll
-        for (int kk = 0; kk < H / 16; ++kk)
-            a3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw3[kk], relu_pack8(a2[kk >> 1], 8 * (kk & 1)), a3, 0, 0, 0);
-        const float yv = a3[0] + b3;
-        const float yo = MODE == GUESS ? __builtin_amdgcn_exp2f((yv * inv_out + A.out_shift) * kLog2of10) : yv;
+        const trnet::sh4 bx = live ? trnet::input_operand(x0, x1, x2) : trnet::sh4_of(0u, 0u);
+        const float yv = net.eval(bx);
+        const float yo = MODE == GUESS ? trnet::temperature(yv, inv_out, A.out_shift) : yv;
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(yo), rout, live ? (uint32_t)s * 4u : kOut, 0, 0);
     };
     // a wave takes steps wave, wave + nwave, ...; the inputs of the next three are in flight
     // while one computes (three register sets, so no step waits on a load issued just before)
-    float a0, a1, a2, b0, b1, b2, c0, c1, c2_;
+    float a0, a1, a2, b0, b1, b2, c0, c1, c2;
     load(wave, a0, a1, a2);
     load(wave + nwave, b0, b1, b2);
-    load(wave + 2 * (int64_t)nwave, c0, c1, c2_);
+    load(wave + 2 * (int64_t)nwave, c0, c1, c2);
     for (int64_t ch = wave; ch < nchunk; ch += 3 * (int64_t)nwave) {
         step(ch, a0, a1, a2);
         load(ch + 3 * (int64_t)nwave, a0, a1, a2);
@@ -418,8 +330,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs A) {
         step(ch + nwave, b0, b1, b2);
         load(ch + 4 * (int64_t)nwave, b0, b1, b2);
         if (ch + 2 * (int64_t)nwave >= nchunk) break;
-        step(ch + 2 * (int64_t)nwave, c0, c1, c2_);
-        load(ch + 5 * (int64_t)nwave, c0, c1, c2_);
+        step(ch + 2 * (int64_t)nwave, c0, c1, c2);
+        load(ch + 5 * (int64_t)nwave, c0, c1, c2);
     }
 }
 

@@ -135,3 +135,26 @@ def test_dust_and_network_tiny_inputs(lib, ctx, n):
         _, yo, _ = oracle.mlp(H, prm.astype(np.float64), x.astype(np.float64), np.zeros(n), round_bf16=True)
         assert np.allclose(y.cpu().numpy(), yo, rtol=1e-2, atol=1e-2 * np.abs(yo).max())
     m.free()
+
+
+def test_learned_one_kernel_equals_staged(lib, ctx):
+    """The learned start in one kernel (guesses kept in registers) and staged (inference into a
+    buffer, then the solve) take the same starting points: identical T_dust and step counts
+    on every state, including a ragged last group of 64."""
+    import torch
+    from paper_2204_09072_amd.guess import features
+    s = W.dust_samples(100_003, seed=44).astype(np.float32)
+    f = features(*(s[:, k].astype(np.float64) for k in range(3)))
+    norm = np.array([*f.mean(0), *(1.0 / f.std(0)), 1.3, 2.0], np.float32)
+    mlp = lib.Mlp(ctx, lib.init_mlp_params(11), norm)
+    rho, u, tg = (torch.from_numpy(np.ascontiguousarray(s[:, k])).cuda() for k in range(3))
+    out = {}
+    for staged in (False, True):
+        t = torch.empty(len(s), device="cuda")
+        it = torch.empty(len(s), dtype=torch.uint8, device="cuda")
+        lib.dust_equilibrium(ctx, rho, u, tg, lib.dust_params(W.SIGMA_SB, W.C_LIGHT, staged=staged), t, it, mlp)
+        ctx.sync()
+        out[staged] = (t.cpu().numpy(), it.cpu().numpy())
+    assert np.array_equal(out[False][0], out[True][0])
+    assert np.array_equal(out[False][1], out[True][1])
+    mlp.free()

@@ -416,6 +416,17 @@ def test_mlp_grad_parity(lib, ctx):
     # relative) near a rounding boundary; away from those the outputs agree to 1e-5
     assert np.median(d) < 1e-5 and np.quantile(d, 0.99) < 1e-3 and d.max() < 1e-2
     assert loss.item() == pytest.approx(lo, rel=1e-3)
+    # many 32-sample steps per wave (the inference loop keeps three steps' inputs in flight):
+    # every sample against the FP64 network
+    nb = 300_001
+    xb = _bf16(np.random.default_rng(5).normal(size=(nb, 3)).astype(np.float32))
+    ob = torch.zeros(nb, device="cuda")
+    m.forward(torch.from_numpy(xb).cuda(), ob)
+    ctx.sync()
+    _, oob, _ = oracle.mlp(H, prm.astype(np.float64), xb.astype(np.float64), round_bf16=True, grad=False)
+    db = np.abs(ob.cpu().numpy() - oob) / np.abs(oob).max()
+    say("forward %d: median %.2e max %.2e" % (nb, np.median(db), db.max()))
+    assert np.median(db) < 1e-5 and db.max() < 1e-2
     g = g.cpu().numpy()
     offs = [0, 3 * H, 4 * H, 4 * H + H * H, 5 * H + H * H, 6 * H + H * H, 6 * H + H * H + 1]
     for a, b in zip(offs[:-1], offs[1:]):
