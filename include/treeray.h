@@ -111,11 +111,9 @@ typedef struct tr_trace_params {
     int32_t bins_per_pass; /* ray segments per walk pass (at most 16); 0 = automatic */
     int32_t chunk;         /* targets taken per work-queue grab; 0 = automatic */
     int32_t waves_per_block; /* waves per block; 0 = automatic */
-    int32_t kernel;        /* 0 = automatic (currently always 1, the faster on every workload
-                              measured), 1 = one wave per target (segments processed in passes
-                              of bins_per_pass radial points), 2 = one block of waves per
-                              target (all segments in LDS, one walk; needs N_side <= 4 and an
-                              opening angle >= 1/8) */
+    int32_t kernel;        /* 0 = automatic, 1 = one wave per target (segments processed in
+                              passes of bins_per_pass radial points; the only kernel); 2 (one
+                              block of waves per target) is withdrawn: TR_EINVAL */
     int32_t per_node_kernel; /* 0 = tabulated angular kernel (tr_alpha_table) for nodes at
                               least 8 edges away and the per-node 8-point kernel for nearer
                               ones; 1 = the per-node kernel for every node */
@@ -174,7 +172,7 @@ int tr_walk_counts(tr_ctx *ctx, const tr_tree *tree, const tr_trace_params *p,
  * [N_pix][3], built on the device and copied to HOST buffers; synchronous. */
 int tr_ray_tables(tr_ctx *ctx, int n_side, int cube_m, int32_t *table, float *dirs);
 
-/* Tabulated angular kernel (Sec. 4.2.1) that nodes at least 8 edges away use: HOST
+/* Tabulated angular kernel (Sec. 4.2) that nodes at least 8 edges away use: HOST
  * int32[6 M M][15][9], per direction cell and distance class c = floor(log2(r^2 / s^2)) =
  * 6 .. 20, pixels 0..3 (ascending), their counts out of 64 sub-points, and a flag for keys
  * whose sub-points reach more than 4 pixels (served by the per-node kernel); synchronous. */

@@ -508,7 +508,7 @@ static int cube_cell(const int64_t *d, int M) {
     return (int)((f * M + i) * M + j);
 }
 
-/* Tabulated angular kernel (Sec. 4.2.1: alpha is tabulated over discrete angles and
+/* Tabulated angular kernel (Sec. 4.2: alpha is tabulated over discrete angles and
  * distances).  For a node at least 8 edges away (r / s >= 8) alpha depends on its direction
  * cell and its distance class c = floor(log2(r^2 / s^2)), c = 6 .. 20 (the last class
  * takes everything farther).  The entry of (cell, c) is the share per pixel of the 4^3

@@ -256,7 +256,7 @@ def tree_export(ctx: Context, tree: Tree):
 def trace_params(n_side, theta=None, cube_m=0, merge=True, j_bg=0.0, bins_per_pass=0, chunk=0,
                  waves_per_block=0, kernel=0, per_node_kernel=False, orientation=0,
                  orient_seed=0) -> TraceParams:
-    """kernel: 0 automatic (the one-wave kernel), 1 one wave per target, 2 one block per target.
+    """kernel: 0 automatic, 1 one wave per target (2, one block per target, is withdrawn).
     per_node_kernel: the 8-point kernel for every node instead of the table for far ones.
     orientation: 0..47 signed axis permutation of the ray set, -1 drawn per target."""
     th = (0, 0) if theta is None else theta

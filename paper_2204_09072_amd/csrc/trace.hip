@@ -75,7 +75,6 @@ struct TraceArgs {
     float j_bg;
     float c_light;
     int kstack;     // ranges per wave stack
-    int fcap;       // cooperative kernel: frontier capacity (child ranges per depth)
     int tab_slot;   // batched launches: which LDS table set the instance uses
     int orient;     // ray-set orientation 0..47, -1 = drawn per target
     int per_node;   // 1: the per-node angular kernel for every node (no table)
@@ -263,7 +262,7 @@ __device__ __forceinline__ void seg_sum_step(int rl, int rid, float &v0, float &
     }
 }
 
-// Tabulated angular kernel (Sec. 4.2.1): nodes at least 8 edges away (r >= 8 s) take the
+// Tabulated angular kernel (Sec. 4.2): nodes at least 8 edges away (r >= 8 s) take the
 // entry of their direction cell and distance class c = floor(log2(r^2 / s^2)), 6 <= c <= 20
 // (larger classes count as 20).  Entry: 64 bits, pixels 0..3 (10 bits each from bit 0),
 // counts 0..2 out of 64 (7 bits each from bit 40; count 3 = 64 - the others) and bit 61 set
@@ -368,14 +367,12 @@ __device__ __forceinline__ float beta_of(int dx, int dy, int dz, int i) {
 // queue entry brings the node's offset from the walk, so the mapping position is not read
 // again and the node's sums and its table entry are fetched side by side.  Otherwise the per-node kernel: the node
 // cube's 2x2x2 sub-points, each binned to a direction cell and its pixel, sorted to find
-// the distinct pixels.  SPLIT: merge flags in flg and thick-content flags in flgt, one bit
-// per segment of the pass each (passes of up to 31 segments); otherwise both in flg (thick
-// bits from bit 16).
-template <bool LDS_TABLE, bool FAR, bool SPLIT = false>
+// the distinct pixels.  Merge flags and thick-content flags share one word per ray in flg
+// (thick bits from bit 16).
+template <bool LDS_TABLE, bool FAR>
 __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid, const int *qnode, const uint32_t *qpk,
                                           int pass_a, int4 c256, int orient, const uint8_t *tab8, float *bins,
-                                          uint32_t *flg, float4 *thick, uint32_t *flgt = nullptr,
-                                          const int *qdx = nullptr, const int *qdy = nullptr,
+                                          uint32_t *flg, float4 *thick, const int *qdx = nullptr, const int *qdy = nullptr,
                                           const int *qdz = nullptr) {
     uint32_t starts = 0;
     int pix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -486,13 +483,8 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
             ft = 1u << seg;
         }
         const uint32_t fm = on ? fbits : 0u;
-        if (SPLIT) {
-            if (fm) atomicOr(flg + px, fm);
-            if (ft) atomicOr(flgt + px, ft);
-        } else {
-            const uint32_t fl = fm | (ft << 16);
-            if (fl) atomicOr(flg + px, fl);
-        }
+        const uint32_t fl = fm | (ft << 16);
+        if (fl) atomicOr(flg + px, fl);
     };
     auto flush = [&](int key, float v0, float v1) {
         // runs of equal keys within rows of 16 lanes (wave-uniform control flow): run id =
@@ -582,115 +574,6 @@ __device__ __forceinline__ void integrate_segment(const float *s, int i, float o
     Fh += __expf(-tau_thin) * eps_thick * Fs;
     tau_thin += tt;
     eps_thick *= (1.0f - f) + f * __expf(-tk);
-}
-
-// One node of the opening-angle walk for target T in pass G (Sec. 4, 4.2), the same test
-// as the one-wave kernel's walk step (written out there, where it allocates registers
-// better): leaves are accepted, h-nodes accepted when s/d < theta and otherwise opened
-// (their child range is returned in `push` unless the pass prunes the subtree); an
-// accepted node whose material can reach the pass is returned as a queue record (`pk`,
-// and whether it is far enough for the tabulated angular kernel).
-struct Target {
-    int tid, tx, ty, tz;
-    int4 c256;
-    int orient;
-};
-struct PassGeo {
-    int a, b, lo_cut, hi_cut, a4, b4;
-    bool last;
-};
-
-template <bool COUNT>
-__device__ __forceinline__ void visit_node(const TraceArgs &A, int node, const Target &T, const PassGeo &G,
-                                           int &n_b, int &n_h, int &n_open, bool &open, uint32_t &push,
-                                           bool &enq, uint32_t &pk, bool &far1, int &fdx, int &fdy,
-                                           int &fdz) {
-    const int4 nd = A.nodes[node];
-    const int4 pfc = A.pcol[node]; // fetched beside the walk record
-    const int depth = (nd.x >> 16) & 15;
-    const bool leaf = (nd.x >> 20) & 1;
-    const bool thick = (nd.x >> 21) & 1;
-    const int s = A.root_edge >> depth;
-    const int vx = (nd.x & 0xffff) - T.tx, vy = (nd.y & 0xffff) - T.ty, vz = nd.z - T.tz;
-    bool acc = false;
-    if (leaf) {
-        if (node != T.tid) {
-            ++n_b;
-            acc = true;
-        }
-    } else {
-        // |v| < 2^12, s < 2^12: d2 and s^2 fit 24 bits
-        const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
-        const int s2 = __mul24(s, s);
-        const bool accept = A.wide_open ? (int64_t)s2 * A.th_den2 < (int64_t)A.th_num2 * d2
-                                        : s2 * A.th_den2 < A.th_num2 * d2;
-        if (accept) {
-            ++n_h;
-            acc = true;
-        } else {
-            ++n_open;
-            bool keep = true;
-            if (!COUNT) {
-                // keep a subtree when r_max + s/4 >= R_a and r_min - s/4 < R_b
-                const int hs = s >> 1, q4 = s >> 2;
-                const int ax = abs(vx), ay = abs(vy), az = abs(vz);
-                const int nx = max(ax - hs, 0), ny = max(ay - hs, 0), nz = max(az - hs, 0);
-                const int fx = ax + hs, fy = ay + hs, fz = az + hs;
-                const int rmin2 = __mul24(nx, nx) + __mul24(ny, ny) + __mul24(nz, nz);
-                const int rmax2 = __mul24(fx, fx) + __mul24(fy, fy) + __mul24(fz, fz);
-                const int lo = G.lo_cut - q4, hi = G.hi_cut + q4;
-                if (lo > 0 && rmax2 < __mul24(lo, lo)) keep = false;
-                if (!G.last && rmin2 >= __mul24(hi, hi)) keep = false;
-            }
-            if (keep) {
-                open = true;
-                push = ((uint32_t)nd.w << 3) |
-                       (uint32_t)(__builtin_popcount((nd.y >> 16) & 255) - 1);
-            }
-        }
-    }
-    if (!COUNT && acc) {
-        // exact integer pre-test in lattice units: the mapping position lies in
-        // the node cube, so r is within [r_min, r_max]; thick material reaches a
-        // further s/2 for the merge flags.  R_i = i^2, so R_i <= r <=> i^4 <= r^2.
-        const int ext = thick && A.merge ? (s >> 1) : 0;
-        bool maybe;
-        if (leaf) {
-            const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
-            if (ext == 0) {
-                maybe = d2 >= G.a4 && (G.last || d2 < G.b4);
-            } else {
-                const int lo = G.a * G.a - ext, hi = G.b * G.b + ext;
-                maybe = (lo <= 0 || d2 >= __mul24(lo, lo)) && (G.last || d2 < __mul24(hi, hi));
-            }
-        } else {
-            const int hs = (s >> 1) + ext;
-            const int ax = abs(vx), ay = abs(vy), az = abs(vz);
-            const int nx = max(ax - hs, 0), ny = max(ay - hs, 0), nz = max(az - hs, 0);
-            const int fx = ax + hs, fy = ay + hs, fz = az + hs;
-            const int rmin2 = __mul24(nx, nx) + __mul24(ny, ny) + __mul24(nz, nz);
-            const int rmax2 = __mul24(fx, fx) + __mul24(fy, fy) + __mul24(fz, fz);
-            maybe = rmax2 >= G.a4 && (G.last || rmin2 < G.b4);
-        }
-        if (maybe) {
-            int dx, dy, dz;
-            if (leaf) {
-                dx = vx * TR_FX; dy = vy * TR_FX; dz = vz * TR_FX;
-            } else {
-                dx = pfc.x - T.c256.x; dy = pfc.y - T.c256.y; dz = pfc.z - T.c256.z;
-            }
-            const SegHit h = seg_hit(dx, dy, dz, s, ext, G.a, G.b, G.last, A.n_bins);
-            if (h.content || h.k1 > h.k0) {
-                enq = true;
-                const int c = dist_class(dx, dy, dz, (31 - __clz(A.root_edge)) - depth);
-                far1 = !A.per_node && c >= kAlphaFar;
-                pk = (h.content ? (uint32_t)(h.i - G.a + 1) : 0u) | ((uint32_t)h.k0 << 6) |
-                     ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) | ((uint32_t)depth << 19) |
-                     ((thick ? 1u : 0u) << 23) | (far1 ? (uint32_t)(c < kAlphaMax ? c : kAlphaMax) << 24 : 0u);
-                fdx = dx; fdy = dy; fdz = dz;
-            }
-        }
-    }
 }
 
 // A trace kernel reads its instance's arguments where it uses them (scalar loads from the
@@ -885,8 +768,8 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
             if (qf >= 64 || (sp == 0 && qf > 0)) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = qf - nq + (lane < nq ? lane : 0);
-                map_queue<LDS_TABLE, true>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick,
-                                                        nullptr, qdx, qdy, qdz);
+                map_queue<LDS_TABLE, true>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick, qdx,
+                                           qdy, qdz);
                 qf -= nq;
                 wave_sync();
             }
@@ -1037,291 +920,6 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
             if (t0 >= hi) break;
             const int t1 = t0 + A.chunk < hi ? t0 + A.chunk : hi;
             for (int ti = t0; ti < t1; ++ti) trace_target<NSLOT, COUNT, LDS_TABLE, ARGS_KERNEL>(0, ti, lds, tab8, thick);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------------------
-// Cooperative trace: one block per CU traces one target at a time.  The segments of all
-// (or, when they do not fit, `bp`) radial points sit once in LDS for the whole block, so a
-// target needs one pass and the tree is walked once.  The walk is level-synchronous: the
-// child ranges of the nodes opened at one depth form the next depth's frontier in LDS, the
-// block's waves take 16 ranges (two nodes per lane) at a time from it with an LDS counter,
-// and one barrier separates depths.  Accepted nodes go to each wave's own queues and are mapped
-// 64 at a time as in k_trace; one lane per ray integrates.
-// ---------------------------------------------------------------------------------------
-constexpr int kMaxLevels = 16;
-
-struct CoopLayout {
-    int bins, flgm, flgt, fr0, fr1, ctl, part, queues, qmeta, total;
-};
-
-__host__ __device__ inline CoopLayout coop_layout(int npix, int bp, int fcap, int waves) {
-    CoopLayout L;
-    int o = 0;
-    L.bins = o;  o += npix * bp * kThin * 4;
-    L.flgm = o;  o += npix * 4;
-    L.flgt = o;  o += npix * 4;
-    L.fr0 = o;   o += fcap * 4;
-    L.fr1 = o;   o += fcap * 4;
-    L.ctl = o;   o += (2 * kMaxLevels + 4) * 4;   // grab[level], count[level], target
-    L.part = o;  o += 4 * 4 * 4;                  // partial sums of up to 4 ray waves
-    L.queues = o; o += waves * 2 * kQueue * 4;
-    L.qmeta = o;  o += waves * kFarQ * 12;
-    L.total = (o + 15) & ~15;
-    return L;
-}
-
-__device__ void coop_target(int ti, char *lds, const CoopLayout &L, int fcap, const uint8_t *tab8,
-                            float4 *thick) {
-    const TraceArgs &A = args_at<ARGS_KERNEL>(0);
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
-    float *bins = reinterpret_cast<float *>(lds + L.bins);
-    uint32_t *flgm = reinterpret_cast<uint32_t *>(lds + L.flgm);
-    uint32_t *flgt = reinterpret_cast<uint32_t *>(lds + L.flgt);
-    uint32_t *fr0 = reinterpret_cast<uint32_t *>(lds + L.fr0), *fr1 = reinterpret_cast<uint32_t *>(lds + L.fr1);
-    int *grab = reinterpret_cast<int *>(lds + L.ctl);
-    int *count = grab + kMaxLevels;
-    float *part = reinterpret_cast<float *>(lds + L.part);
-    int *qnode = reinterpret_cast<int *>(lds + L.queues) + wv * 2 * kQueue;
-    uint32_t *qpk = reinterpret_cast<uint32_t *>(qnode + kQueue);
-    int *qdx = reinterpret_cast<int *>(lds + L.qmeta) + wv * 3 * kFarQ;
-    int *qdy = qdx + kFarQ, *qdz = qdy + kFarQ;
-    const int tid = A.targets[ti];
-    const int4 tr = A.nodes[tid];
-    const int tx = tr.x & 0xffff, ty = tr.y & 0xffff, tz = tr.z;
-    const int4 c256 = make_int4(tx * TR_FX, ty * TR_FX, tz * TR_FX, 0);
-    const int orient = target_orient(A.orient, A.orient_seed, A.leaf_cell[tid]);
-    const Target T{tid, tx, ty, tz, c256, orient};
-    // ray state of this thread's ray (threads 0 .. npix-1)
-    const int h = threadIdx.x;
-    const bool ray = h < A.npix;
-    float tau_thin = 0.0f, eps_thick = 1.0f, Fh = 0.0f;
-    int run_i = 0;
-    float acc[kFields] = {0, 0, 0, 0, 0, 0};
-    int n_b = 0, n_h = 0, n_open = 0; // not reported here
-    for (int ps = 0; ps < A.n_pass; ++ps) {
-        Pass P;
-        P.a = 1 + ps * A.bp;
-        P.b = P.a + A.bp;
-        if (P.b > A.n_bins + 1) P.b = A.n_bins + 1;
-        const int lo_cut = P.a * P.a, hi_cut = P.b * P.b;
-        const PassGeo G{P.a, P.b, lo_cut, hi_cut, lo_cut * lo_cut, hi_cut * hi_cut, P.b > A.n_bins};
-        const int nf = A.npix * A.bp * kThin;
-        for (int k = threadIdx.x; k < nf; k += blockDim.x) bins[k] = 0.0f;
-        for (int k = threadIdx.x; k < A.npix; k += blockDim.x) {
-            flgm[k] = 0u;
-            flgt[k] = 0u;
-        }
-        for (int k = threadIdx.x; k < 2 * kMaxLevels; k += blockDim.x) grab[k] = 0;
-        if (threadIdx.x == 0) {
-            fr0[0] = 0u; // the root: first node 0, one node
-            count[0] = 1;
-        }
-        __syncthreads();
-        int qf = 0, qs = 0;
-        for (int lev = 0; lev < kMaxLevels; ++lev) {
-            const int nF = min(count[lev], fcap);
-            if (nF == 0) break;
-            const uint32_t *Fc = (lev & 1) ? fr1 : fr0;
-            uint32_t *Fn = (lev & 1) ? fr0 : fr1;
-            for (;;) {
-                const TraceArgs &A = args_at<ARGS_KERNEL>(0);
-                // 16 ranges per grab: every lane tests up to two nodes, one from each half
-                int c = 0;
-                if (lane == 0) c = atomicAdd(grab + lev, 16);
-                c = __builtin_amdgcn_readfirstlane(c);
-                if (c < nF) {
-                    const uint64_t below = (1ull << lane) - 1ull;
-#pragma unroll
-                    for (int half = 0; half < 2; ++half) {
-                        const int c0 = c + 8 * half;
-                        const int npop = nF - c0 < 8 ? nF - c0 : 8;
-                        const int r = lane >> 3, k = lane & 7;
-                        const uint32_t rg = r < npop ? Fc[c0 + r] : 0u;
-                        const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
-                        bool open = false, enq = false, far1 = false;
-                        uint32_t push = 0, pk = 0;
-                        int fdx = 0, fdy = 0, fdz = 0;
-                        if (node >= 0)
-                            visit_node<false>(A, node, T, G, n_b, n_h, n_open, open, push, enq, pk, far1, fdx, fdy,
-                                              fdz);
-                        const uint64_t bal = __ballot(open);
-                        const int npush = __builtin_popcountll(bal);
-                        if (npush) {
-                            int base = 0;
-                            if (lane == 0) base = atomicAdd(count + lev + 1, npush);
-                            base = __builtin_amdgcn_readfirstlane(base);
-                            const int pos = base + __builtin_popcountll(bal & below);
-                            if (open && pos < fcap) Fn[pos] = push;
-                            if (base + npush > fcap && lane == 0) atomicOr(A.err, 4);
-                        }
-                        const uint64_t fb = __ballot(enq && far1), gb = __ballot(enq && !far1);
-                        if (enq) {
-                            const int qp = far1 ? qf + __builtin_popcountll(fb & below)
-                                                 : kQueue - 1 - qs - __builtin_popcountll(gb & below);
-                            qnode[qp] = node;
-                            qpk[qp] = pk;
-                            if (far1) {
-                                qdx[qp] = fdx;
-                                qdy[qp] = fdy;
-                                qdz[qp] = fdz;
-                            }
-                        }
-                        qf += __builtin_popcountll(fb);
-                        qs += __builtin_popcountll(gb);
-                        wave_sync();
-                        if (qf >= 64) {
-                            const int e = qf - 64 + lane;
-                            map_queue<true, true, true>(A, e, true, qnode, qpk, P.a, c256, orient, tab8, bins, flgm,
-                                                              thick, flgt, qdx, qdy, qdz);
-                            qf -= 64;
-                            wave_sync();
-                        }
-                        if (qs >= 64) {
-                            const int e = kQueue - qs + lane;
-                            map_queue<true, false, true>(A, e, true, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick,
-                                                         flgt);
-                            qs -= 64;
-                            wave_sync();
-                        }
-                    }
-                } else {
-                    break;
-                }
-            }
-            __syncthreads(); // every wave has finished depth lev and appended depth lev + 1
-        }
-        // what is left in this wave's queues
-        while (qf > 0 || qs > 0) {
-            if (qf > 0) {
-                const int nq = qf >= 64 ? 64 : qf;
-                const int e = qf - nq + (lane < nq ? lane : 0);
-                map_queue<true, true, true>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt,
-                                                  qdx, qdy, qdz);
-                qf -= nq;
-                wave_sync();
-            }
-            if (qs > 0) {
-                const int nq = qs >= 64 ? 64 : qs;
-                const int e = kQueue - qs + (lane < nq ? lane : 0);
-                map_queue<true, false, true>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flgm, thick, flgt);
-                qs -= nq;
-                wave_sync();
-            }
-        }
-        __threadfence_block();
-        __syncthreads();
-        // integrate the pass's segments outwards, one thread per ray
-        if (ray) {
-            const uint32_t fm = flgm[h], ft = flgt[h];
-            for (int i = P.a; i < P.b; ++i) {
-                const float *th = bins + (h * A.bp + (i - P.a)) * kThin;
-                float v[kFields] = {th[0], th[1], 0.0f, 0.0f, 0.0f, 0.0f};
-                if ((ft >> (i - P.a)) & 1u) {
-                    float *tk = reinterpret_cast<float *>(thick + h * A.bp + (i - P.a));
-#pragma unroll
-                    for (int f = 0; f < 4; ++f) v[2 + f] = atomicExch(tk + f, 0.0f);
-                }
-                if (run_i == 0) {
-                    run_i = i;
-#pragma unroll
-                    for (int f = 0; f < kFields; ++f) acc[f] = v[f];
-                } else {
-                    const float Tq = (float)run_i * rcp((float)i);
-                    const float T4 = (Tq * Tq) * (Tq * Tq);
-                    acc[0] += T4 * v[0];
-                    acc[1] += T4 * v[1];
-                    acc[2] += v[2];
-                    acc[3] += v[3];
-                    acc[4] += v[4];
-                    acc[5] += T4 * v[5];
-                }
-                const bool link = ((fm >> (i - P.a)) & 1u) && i < A.n_bins;
-                if (!link) {
-                    integrate_segment(acc, run_i, A.omega, tau_thin, eps_thick, Fh);
-                    run_i = 0;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // finalisation (Sec. 4.4): F = -sum F^h n^h, J = sum F^h / 4 pi + J_src
-    float js = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    if (ray) {
-        const float F = Fh + __expf(-tau_thin) * eps_thick * A.omega * A.j_bg;
-        const float4 n = A.dirs[h];
-        js = F;
-        fx = -F * n.x;
-        fy = -F * n.y;
-        fz = -F * n.z;
-    }
-    const int rw = (A.npix + 63) >> 6;
-    if (wv < rw) {
-        for (int o = 32; o > 0; o >>= 1) {
-            js += __shfl_xor(js, o);
-            fx += __shfl_xor(fx, o);
-            fy += __shfl_xor(fy, o);
-            fz += __shfl_xor(fz, o);
-        }
-        if (lane == 0) {
-            part[4 * wv] = js;
-            part[4 * wv + 1] = fx;
-            part[4 * wv + 2] = fy;
-            part[4 * wv + 3] = fz;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        js = part[0]; fx = part[1]; fy = part[2]; fz = part[3];
-        for (int w = 1; w < rw; ++w) {
-            js += part[4 * w];
-            fx += part[4 * w + 1];
-            fy += part[4 * w + 2];
-            fz += part[4 * w + 3];
-        }
-        const int cell = A.leaf_cell[tid];
-        const float src = A.cell_src[cell];
-        float Jv = js * (0.25f / kPiF);
-        if (src > 0.0f) {
-            const float e = (float)(A.root_edge >> ((tr.x >> 16) & 15));
-            Jv += -expm1f(-0.5f * A.cell_tau[cell]) * src / (4.0f * kPiF * (e * e));
-        }
-        orient_back(orient, fx, fy, fz); // the flux back to the grid's axes
-        A.J[cell] = Jv;
-        A.F[cell] = fx;
-        A.F[A.n_cells + cell] = fy;
-        A.F[2 * A.n_cells + cell] = fz;
-        if (A.u_rad) A.u_rad[cell] = 4.0f * kPiF * Jv / A.c_light;
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_trace_coop(TraceArgs A) {
-    extern __shared__ __align__(16) char smem[];
-    const int ncell = 6 << (2 * A.log2m);
-    uint8_t *t = reinterpret_cast<uint8_t *>(smem);
-    for (int k = threadIdx.x; k < ncell; k += blockDim.x) t[k] = (uint8_t)A.table[k];
-
-    __syncthreads();
-    const uint8_t *tab8 = t;
-    char *lds = smem + A.lds_table;
-    const int fcap = A.fcap;
-    const CoopLayout L = coop_layout(A.npix, A.bp, fcap, blockDim.x >> 6);
-    int *target = reinterpret_cast<int *>(lds + L.ctl) + 2 * kMaxLevels;
-    float4 *thick = A.thick + (int64_t)blockIdx.x * A.npix * A.bp;
-    const int home = blockIdx.x & 7;
-    const int per = (A.n_targets + 7) >> 3;
-    for (int x = 0; x < 8; ++x) {
-        const int r = (home + x) & 7;
-        const int lo = r * per;
-        const int hi = min(lo + per, A.n_targets);
-        for (;;) {
-            if (threadIdx.x == 0) *target = atomicAdd(A.work + r, 1);
-            __syncthreads();
-            const int ti = *target + lo;
-            __syncthreads();
-            if (ti >= hi) break;
-            coop_target(ti, lds, L, fcap, tab8, thick);
         }
     }
 }
@@ -1544,43 +1142,6 @@ int ensure_thick(tr_ctx *ctx, int64_t need) {
     return TR_OK;
 }
 
-// Cooperative launch (one block per CU, one target per block) when the case allows it:
-// direction tables in LDS, opening angle >= 1/8 (the per-depth frontier stays below
-// (4/3) pi (1/theta + 1)^3 ranges), and the segments of at least one radial point per
-// pass next to a frontier of kCoopFrontier ranges.  Returns TR_ENOTSUP otherwise.
-constexpr int TR_ENOTSUP = 1;
-constexpr int kCoopFrontier = 4096;
-
-int launch_coop(tr_ctx *ctx, Inst &I, const tr_trace_params *p, int lds_table) {
-    TraceArgs &A = I.A;
-    const int npix = I.npix;
-    if (npix > 256) return TR_ENOTSUP;
-    if ((int64_t)A.th_den2 > 64 * (int64_t)A.th_num2) return TR_ENOTSUP;
-    int waves = p->waves_per_block > 0 ? p->waves_per_block : 16;
-    if (waves > 16) waves = 16;
-    if (waves * 64 < npix) waves = (npix + 63) / 64;
-    int bp = p->bins_per_pass > 0 ? p->bins_per_pass : A.n_bins;
-    if (bp > A.n_bins) bp = A.n_bins;
-    if (bp > 31) bp = 31;
-    while (bp > 1 && lds_table + coop_layout(npix, bp, kCoopFrontier, waves).total > kLdsCu) --bp;
-    const int lds = lds_table + coop_layout(npix, bp, kCoopFrontier, waves).total;
-    if (lds > kLdsCu) return TR_ENOTSUP;
-    A.bp = bp;
-    A.n_pass = (int)tr_div_up(A.n_bins, bp);
-    A.fcap = kCoopFrontier;
-    A.lds_table = lds_table;
-    A.per_block = 1;
-    A.chunk = 1;
-    const int grid = ctx->n_cu;
-    int rc = ensure_thick(ctx, (int64_t)grid * npix * bp);
-    if (rc) return rc;
-    A.thick = ctx->ws_thick;
-    k_zero_int<<<1, 64, 0, ctx->stream>>>(ctx->d_ctl, 8);
-    hipLaunchKernelGGL(k_trace_coop, dim3(grid), dim3(64 * waves), lds, ctx->stream, A);
-    if (hipGetLastError() != hipSuccess) return tr_fail(ctx, TR_EHIP, "cooperative trace kernel launch failed");
-    return TR_OK;
-}
-
 int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float *J, float *F,
                  float *u_rad, int32_t *counters, bool count) {
     if (!ctx) return TR_EINVAL;
@@ -1588,19 +1149,14 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     Inst I;
     int rc = setup_instance(ctx, t, p, J, F, u_rad, counters, count, I);
     if (rc) return rc;
-    if (p->kernel < 0 || p->kernel > 2) return tr_fail(ctx, TR_EINVAL, "kernel must be 0, 1 or 2");
+    if (p->kernel == 2)
+        return tr_fail(ctx, TR_EINVAL, "kernel 2 (one block of waves per target) is withdrawn: the one-wave kernel "
+                       "(0 or 1) was faster on every workload measured");
+    if (p->kernel < 0 || p->kernel > 1) return tr_fail(ctx, TR_EINVAL, "kernel must be 0 or 1");
     const int npix = I.npix;
     const bool tab_lds = !count && table_in_lds(npix);
     const int lds_table = tab_lds ? table_bytes(I.M) : 0;
     const int max_waves = max_waves_for(npix);
-    // the one-block-per-target kernel only on request: the one-wave kernel is faster on every
-    // workload measured (128^3 core 1.46 s against 1.75 s; AMR 256^3-equivalent, 10 passes,
-    // 2.12 s against 2.30 s for one pass per target)
-    if (!count && p->kernel == 2) {
-        rc = launch_coop(ctx, I, p, npix <= 256 ? table_bytes(I.M) : 0);
-        if (rc != TR_ENOTSUP) return rc;
-        return tr_fail(ctx, TR_EINVAL, "the one-block-per-target kernel does not fit this case");
-    }
     set_bp(I, choose_bp(I, p->bins_per_pass, lds_table, waves_cu_for(npix, true), count), count);
     TraceArgs &A = I.A;
     A.chunk = p->chunk > 0 ? p->chunk : 1; // one target per grab: a short tail (128^3 core: 1.59 s, 1.61 s with 4)

@@ -35,6 +35,17 @@ def say(*a):
     print(*a, flush=True)
 
 
+# The one-block-per-target trace kernel (kernel = 2) is withdrawn: it was slower than the
+# one-wave kernel on every workload measured, and a variant of its walk stopped making
+# progress on the GPU without a cause that could be shown.  Its cases stay, skipped.
+WITHDRAWN = "kernel 2 (one block per target) is withdrawn; the library rejects it"
+
+
+def _k(*args):
+    """A parameter set, skipped when its kernel (the last value) is the withdrawn one."""
+    return pytest.param(*args, marks=pytest.mark.skip(reason=WITHDRAWN)) if args[-1] == 2 else pytest.param(*args)
+
+
 def _amr_small(seed=3, stars=True):
     rng = np.random.default_rng(seed)
     blocks = []
@@ -156,11 +167,11 @@ def _check_trace(J, F, Jo, Fo):
 
 
 # kernel 1: one wave per target (segments in passes); kernel 2: one block per target
-@pytest.mark.parametrize("case,bpp,kernel", [
+@pytest.mark.parametrize("case,bpp,kernel", [_k(*c) for c in [
     ("sphere16", 0, 1), ("turb32", 0, 1), ("turb32", 3, 1), ("amr_small", 0, 1), ("amr_small", 2, 1),
     ("padded40", 0, 1), ("core32", 1, 1),
     ("sphere16", 0, 2), ("turb32", 0, 2), ("turb32", 5, 2), ("amr_small", 0, 2), ("amr_small", 3, 2),
-    ("padded40", 0, 2), ("core32", 0, 2)])
+    ("padded40", 0, 2), ("core32", 0, 2)]])
 def test_trace_parity_all_targets(lib, ctx, case, bpp, kernel):
     from paper_2204_09072_amd.run import trace
     w = TREE_CASES[case]()
@@ -173,7 +184,8 @@ def test_trace_parity_all_targets(lib, ctx, case, bpp, kernel):
     assert np.allclose(U.cpu().numpy(), 4 * np.pi * J.cpu().numpy() / w.units[1], rtol=1e-6)
 
 
-@pytest.mark.parametrize("case,kernel", [("turb32", 1), ("amr_small", 2), ("padded40", 1)])
+@pytest.mark.parametrize("case,kernel", [_k(*c) for c in [("turb32", 1), ("amr_small", 2), ("padded40", 1),
+                                                          ("amr_small", 1)]])
 def test_trace_parity_per_node_kernel(lib, ctx, case, kernel):
     """The per-node 8-point kernel for every node (no table) against the oracle run the
     same way."""
@@ -199,7 +211,7 @@ EDGE_CASES = {
 
 
 @pytest.mark.parametrize("case", list(EDGE_CASES))
-@pytest.mark.parametrize("kernel,bpp", [(1, 0), (1, 1), (2, 0)])
+@pytest.mark.parametrize("kernel,bpp", [_k(1, 0), _k(1, 1), pytest.param(2, 0, marks=pytest.mark.skip(reason=WITHDRAWN))])
 def test_trace_parity_edge_cases(lib, ctx, case, kernel, bpp):
     """Degenerate grids, every target against the oracle, both kernels (one radial point per
     pass for the one-wave kernel as well: every merge run crosses passes)."""
@@ -361,6 +373,11 @@ def test_build_tree_rejects_bad_grids(lib, ctx):
     with pytest.raises(lib.TreerayError):
         lib.trace_rays(ctx, tree, lib.trace_params(3), torch.empty(4096, device="cuda"),
                        torch.empty((3, 4096), device="cuda"))
+    # the withdrawn one-block kernel is refused with a message, before any launch
+    with pytest.raises(lib.TreerayError) as e:
+        lib.trace_rays(ctx, tree, lib.trace_params(1, kernel=2), torch.empty(4096, device="cuda"),
+                       torch.empty((3, 4096), device="cuda"))
+    assert e.value.code == lib.TR_EINVAL and "withdrawn" in str(e.value)
 
 
 # ----------------------------------------------------------------------------------

@@ -644,7 +644,7 @@ def test_uv_rad_pressure_limits():
 
 
 # ----------------------------------------------------------------------------------
-# tabulated angular kernel (Sec. 4.2.1)
+# tabulated angular kernel (Sec. 4.2)
 # ----------------------------------------------------------------------------------
 def _cell_dirs(M):
     """Unit centre direction of every direction cell (face f = 2 axis + sign, i and j
