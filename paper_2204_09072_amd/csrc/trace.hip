@@ -162,14 +162,13 @@ __device__ __forceinline__ uint32_t exact_div(uint32_t num, uint32_t den, float 
 // lower axis, then floor(M (d_a + |d_m|) / (2 |d_m|)) on the other two axes)
 __device__ __forceinline__ int cube_cell(int dx, int dy, int dz, int log2m) {
     const int ax = abs(dx), ay = abs(dy), az = abs(dz);
-    int f, m, ua, ub;
-    if (ax >= ay && ax >= az) {
-        m = ax; f = dx < 0 ? 1 : 0; ua = dy + m; ub = dz + m;
-    } else if (ay >= az) {
-        m = ay; f = dy < 0 ? 3 : 2; ua = dx + m; ub = dz + m;
-    } else {
-        m = az; f = dz < 0 ? 5 : 4; ua = dx + m; ub = dy + m;
-    }
+    // the face by selects (no divergent branches): x when it is the largest (ties to the
+    // lower axis), else y when it is at least z, else z
+    const bool fx = (ax >= ay) & (ax >= az), fy = !fx & (ay >= az);
+    const int m = fx ? ax : (fy ? ay : az);
+    const int lead = fx ? dx : (fy ? dy : dz);
+    const int f = (fx ? 0 : (fy ? 2 : 4)) + (lead < 0 ? 1 : 0);
+    const int ua = (fx ? dy : dx) + m, ub = (fy | fx ? dz : dy) + m;
     const uint32_t den = 2u * (uint32_t)m;
     const float rc = rcp((float)den);
     const int Mm1 = (1 << log2m) - 1;
@@ -646,7 +645,15 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
         if (lane == 0) stk[0] = 0u; // the root: first node 0, one node
         int sp = 1, qf = 0, qs = 0; // stack depth, far and near queue lengths
         wave_sync();
-        while (sp > 0 || qf > 0 || qs > 0) {
+        for (;;) {
+            // The three counts are the same on every lane (they change only by ballot
+            // counts and kernel arguments); read from the first lane they are scalar values
+            // to the compiler too, so the walk's control flow is scalar branches rather than
+            // execution-mask updates.  Every lane is active here (top level of the loop).
+            sp = __builtin_amdgcn_readfirstlane(sp);
+            qf = __builtin_amdgcn_readfirstlane(qf);
+            qs = __builtin_amdgcn_readfirstlane(qs);
+            if (sp <= 0 && qf <= 0 && qs <= 0) break;
             if (sp > 0) {
                 const int npop = sp < 8 ? sp : 8;
                 const int r = lane >> 3, k = lane & 7;
