@@ -2,8 +2,9 @@
 
 Bars: tree topology, keys, flags, integer fields and walk counts bit-exact; node FP32
 fields bit-exact except those carrying the in-cell star extinction exp(-tau/2) (1 ulp);
-J within 1e-4 relative; F and a_RP per component within 1e-4 * 4 pi J; T_dust within
-1e-5 relative of the FP64 bracketed root.
+J within 1e-4 relative; F per component within 1e-4 * 4 pi J; a_RP per component within
+1e-4 (kappa / c) phi_RP 4 pi J of its cell; T_dust within 1e-5 relative of the FP64
+bracketed root.
 """
 import numpy as np
 import pytest
