@@ -460,7 +460,8 @@ def batch_c4(T, ctx, reps):
     return {"value": rays / (ms / 1000.0), "unit": "target-ray evaluations/s", "ms_per_launch": round(ms, 2),
             "replays": reps, "instances": len(ws), "cells": int(cells), "target_rays": int(rays),
             "tuned": {"bins_per_pass": tun.bins_per_pass, "waves_per_block": tun.waves_per_block,
-                      "chunk": tun.chunk, "sample_ms": round(tun.sample_ms, 3), "tune_seconds": round(t_tune, 2)},
+                      "chunk": tun.chunk, "widest_pass": tun.widest_pass, "waves_used": tun.waves_used,
+                      "sample_ms": round(tun.sample_ms, 3), "tune_seconds": round(t_tune, 2)},
             "setup_seconds": round(t_setup, 2),
             "workload": "64 instances, edge uniform over {32, 40, ..., 96} (8^3 blocks), lognormal sigma=1.5, "
                         "kappa 0.1-10, 0-4 stars of L=1, N_side 2 or 4, code units; one autotuned persistent "

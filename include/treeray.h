@@ -154,10 +154,22 @@ int tr_batch_launch_eager(tr_batch *b);
  * descent), keeps the fastest and re-captures the graph.  Synchronous.  The outputs of
  * the sampled targets are overwritten. */
 typedef struct tr_batch_tuning {
-    int32_t bins_per_pass, waves_per_block, chunk;
-    float sample_ms; /* time of the tuned launch on the sample */
+    int32_t bins_per_pass;   /* segments per pass; 0 = the longest pass each instance fits */
+    int32_t waves_per_block; /* 0 = as many as the LDS holds */
+    int32_t chunk;           /* targets per work-queue grab; 0 = 1 */
+    float sample_ms;         /* output: time of the tuned launch on the sample (0 if not timed) */
+    int32_t widest_pass;     /* output: most segments per pass of any instance under the setting */
+    int32_t waves_used;      /* output: waves per block under the setting */
 } tr_batch_tuning;
 int tr_batch_tune(tr_batch *b, int sample_stride, tr_batch_tuning *best);
+/* The batch's current setting (outputs filled as by tr_batch_tune). */
+int tr_batch_get_tuning(const tr_batch *b, tr_batch_tuning *out);
+/* Applies a setting, for instance one tr_batch_tune found in an earlier run and stored
+ * (bins_per_pass, waves_per_block, chunk are read; the outputs are ignored), and
+ * re-captures the graph, so that a cached tuning costs no new search.  TR_EINVAL for a
+ * negative field or a setting that does not fit the LDS, in which case the batch keeps its
+ * previous setting.  Synchronous. */
+int tr_batch_set_tuning(tr_batch *b, const tr_batch_tuning *t);
 void tr_batch_free(tr_batch *b);
 /* One-shot batched trace (build descriptors, one persistent launch, free); synchronous. */
 int tr_trace_rays_batched(tr_ctx *ctx, int n, const tr_tree *const *trees, const tr_trace_params *p,
@@ -253,6 +265,16 @@ int tr_mlp_create(tr_ctx *ctx, const float *params_host, const float *norm_host 
                   shift[3], scale[3], out_shift, out_scale */, tr_mlp **out);
 void tr_mlp_free(tr_mlp *mlp);
 int tr_mlp_get_params(tr_ctx *ctx, const tr_mlp *mlp, float *params_host);
+/* Training state, for checkpoint and resume: FP32 parameters, Adam's first and second
+ * moments (HOST float[n_params] each; any may be NULL to skip it), the number of Adam steps
+ * taken (NULL to skip) and the normalisation (HOST float[8] or NULL).  Synchronous. */
+int tr_mlp_get_state(tr_ctx *ctx, const tr_mlp *mlp, float *params_host, float *adam_m_host,
+                     float *adam_v_host, int64_t *steps, float *norm_host);
+/* Restores a state read by tr_mlp_get_state into a network (NULL moments restart them at
+ * zero); the next tr_mlp_train_step is Adam step steps + 1, with that step's bias
+ * correction.  TR_EINVAL for NULL params or negative steps.  Synchronous. */
+int tr_mlp_set_state(tr_ctx *ctx, tr_mlp *mlp, const float *params_host, const float *adam_m_host,
+                     const float *adam_v_host, int64_t steps);
 /* Forward only: x device float[n][3] (already normalised) -> y device float[n]; n = 0 does
  * nothing (x and y may then be NULL). */
 int tr_mlp_forward(tr_ctx *ctx, const tr_mlp *mlp, int64_t n, const float *x, float *y);

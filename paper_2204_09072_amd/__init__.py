@@ -56,7 +56,7 @@ class TraceParams(C.Structure):
 
 class BatchTuning(C.Structure):
     _fields_ = [("bins_per_pass", C.c_int32), ("waves_per_block", C.c_int32), ("chunk", C.c_int32),
-                ("sample_ms", C.c_float)]
+                ("sample_ms", C.c_float), ("widest_pass", C.c_int32), ("waves_used", C.c_int32)]
 
 
 class UvParams(C.Structure):
@@ -94,6 +94,8 @@ _sig("tr_batch_create", _I, [_P, _I, _P, _P, _P, _P, _P, C.POINTER(_P)])
 _sig("tr_batch_launch", _I, [_P])
 _sig("tr_batch_launch_eager", _I, [_P])
 _sig("tr_batch_tune", _I, [_P, _I, C.POINTER(BatchTuning)])
+_sig("tr_batch_get_tuning", _I, [_P, C.POINTER(BatchTuning)])
+_sig("tr_batch_set_tuning", _I, [_P, C.POINTER(BatchTuning)])
 _sig("tr_batch_free", None, [_P])
 _sig("tr_trace_rays_batched", _I, [_P, _I, _P, _P, _P, _P, _P])
 _sig("tr_ray_tables", _I, [_P, _I, _I, _P, _P])
@@ -110,6 +112,8 @@ _sig("tr_mlp_n_params", _I, [])
 _sig("tr_mlp_create", _I, [_P, _P, _P, C.POINTER(_P)])
 _sig("tr_mlp_free", None, [_P])
 _sig("tr_mlp_get_params", _I, [_P, _P, _P])
+_sig("tr_mlp_get_state", _I, [_P, _P, _P, _P, _P, _P, _P])
+_sig("tr_mlp_set_state", _I, [_P, _P, _P, _P, _P, C.c_int64])
 _sig("tr_mlp_forward", _I, [_P, _P, C.c_int64, _P, _P])
 _sig("tr_mlp_grad", _I, [_P, _P, C.c_int64, _P, _P, _P, _P])
 _sig("tr_mlp_train_step", _I, [_P, _P, C.c_int64, _P, _P, C.c_float, _P])
@@ -304,6 +308,15 @@ class Batch:
         self.ctx.check(_lib.tr_batch_tune(self.h, int(sample_stride), C.byref(out)))
         return out
 
+    def get_tuning(self) -> BatchTuning:
+        out = BatchTuning()
+        self.ctx.check(_lib.tr_batch_get_tuning(self.h, C.byref(out)))
+        return out
+
+    def set_tuning(self, bins_per_pass=0, waves_per_block=0, chunk=0):
+        t = BatchTuning(int(bins_per_pass), int(waves_per_block), int(chunk), 0.0, 0, 0)
+        self.ctx.check(_lib.tr_batch_set_tuning(self.h, C.byref(t)))
+
     def free(self, _free=_lib.tr_batch_free):
         if getattr(self, "h", None):
             _free(self.h)
@@ -389,6 +402,21 @@ class Mlp:
         out = np.zeros(MLP_NPARAM, np.float32)
         self.ctx.check(_lib.tr_mlp_get_params(self.ctx.h, self.h, _ptr(out)))
         return out
+
+    def get_state(self) -> dict:
+        """Training state: params, adam_m, adam_v (float32 arrays), steps, norm."""
+        prm, m1, m2 = (np.zeros(MLP_NPARAM, np.float32) for _ in range(3))
+        norm = np.zeros(8, np.float32)
+        steps = C.c_int64(0)
+        self.ctx.check(_lib.tr_mlp_get_state(self.ctx.h, self.h, _ptr(prm), _ptr(m1), _ptr(m2),
+                                             C.byref(steps), _ptr(norm)))
+        return {"params": prm, "adam_m": m1, "adam_v": m2, "steps": int(steps.value), "norm": norm}
+
+    def set_state(self, params, adam_m=None, adam_v=None, steps=0):
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in (params, adam_m, adam_v)]
+        for a in arrs:
+            assert a is None or a.shape == (MLP_NPARAM,)
+        self.ctx.check(_lib.tr_mlp_set_state(self.ctx.h, self.h, *[_ptr(a) for a in arrs], int(steps)))
 
     def forward(self, x, y):
         self.ctx.check(_lib.tr_mlp_forward(self.ctx.h, self.h, int(x.shape[0]), _ptr(x), _ptr(y)))

@@ -439,6 +439,39 @@ extern "C" int tr_mlp_get_params(tr_ctx *ctx, const tr_mlp *m, float *params) {
     return TR_OK;
 }
 
+extern "C" int tr_mlp_get_state(tr_ctx *ctx, const tr_mlp *m, float *params, float *adam_m, float *adam_v,
+                                int64_t *steps, float *norm) {
+    if (!ctx) return TR_EINVAL;
+    if (!m) return tr_fail(ctx, TR_EINVAL, "tr_mlp_get_state: null network");
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    const size_t b = sizeof(float) * MLP_NPARAM;
+    if (params) TR_HIP(ctx, hipMemcpyAsync(params, m->p, b, hipMemcpyDeviceToHost, ctx->stream));
+    if (adam_m) TR_HIP(ctx, hipMemcpyAsync(adam_m, m->m, b, hipMemcpyDeviceToHost, ctx->stream));
+    if (adam_v) TR_HIP(ctx, hipMemcpyAsync(adam_v, m->v, b, hipMemcpyDeviceToHost, ctx->stream));
+    TR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (steps) *steps = m->step;
+    if (norm)
+        for (int k = 0; k < 8; ++k) norm[k] = m->norm[k];
+    return TR_OK;
+}
+
+extern "C" int tr_mlp_set_state(tr_ctx *ctx, tr_mlp *m, const float *params, const float *adam_m,
+                                const float *adam_v, int64_t steps) {
+    if (!ctx) return TR_EINVAL;
+    if (!m || !params || steps < 0) return tr_fail(ctx, TR_EINVAL, "tr_mlp_set_state: bad argument");
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    const size_t b = sizeof(float) * MLP_NPARAM;
+    TR_HIP(ctx, hipMemcpyAsync(m->p, params, b, hipMemcpyHostToDevice, ctx->stream));
+    if (adam_m) TR_HIP(ctx, hipMemcpyAsync(m->m, adam_m, b, hipMemcpyHostToDevice, ctx->stream));
+    else k_fill<<<tr_div_up(MLP_NPARAM, 256), 256, 0, ctx->stream>>>(m->m, MLP_NPARAM, 0.0f);
+    if (adam_v) TR_HIP(ctx, hipMemcpyAsync(m->v, adam_v, b, hipMemcpyHostToDevice, ctx->stream));
+    else k_fill<<<tr_div_up(MLP_NPARAM, 256), 256, 0, ctx->stream>>>(m->v, MLP_NPARAM, 0.0f);
+    k_round<<<tr_div_up(MLP_NPARAM, 256), 256, 0, ctx->stream>>>(m->p, m->wq, MLP_NPARAM);
+    TR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    m->step = steps;
+    return TR_OK;
+}
+
 extern "C" int tr_mlp_forward(tr_ctx *ctx, const tr_mlp *m, int64_t n, const float *x, float *y) {
     if (!ctx) return TR_EINVAL;
     if (!m || n < 0) return tr_fail(ctx, TR_EINVAL, "tr_mlp_forward: bad argument");

@@ -14,9 +14,8 @@ struct tr_mlp {
     tr_ctx *ctx = nullptr;
     float *p = nullptr;       // FP32 master parameters
     float *wq = nullptr;      // parameters rounded to bfloat16 (held as float)
-    uint16_t *w16 = nullptr;  // bfloat16 bits of W2 for the matrix cores
     float *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
-    int step = 0;
+    int64_t step = 0;         // Adam steps taken
     float norm[8] = {0, 0, 0, 1, 1, 1, 0, 1};
 };
 

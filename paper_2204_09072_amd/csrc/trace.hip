@@ -168,7 +168,7 @@ __device__ __forceinline__ int cube_cell(int dx, int dy, int dz, int log2m) {
     const int m = fx ? ax : (fy ? ay : az);
     const int lead = fx ? dx : (fy ? dy : dz);
     const int f = (fx ? 0 : (fy ? 2 : 4)) + (lead < 0 ? 1 : 0);
-    const int ua = (fx ? dy : dx) + m, ub = (fy | fx ? dz : dy) + m;
+    const int ua = (fx ? dy : dx) + m, ub = ((fy | fx) ? dz : dy) + m;
     const uint32_t den = 2u * (uint32_t)m;
     const float rc = rcp((float)den);
     const int Mm1 = (1 << log2m) - 1;
@@ -1321,6 +1321,19 @@ int batch_enqueue(tr_batch *b, hipStream_t st, bool sample) {
     return TR_OK;
 }
 
+// the batch's current setting as tr_batch_tuning: the knobs as set (0 = automatic) and the
+// widest pass any instance takes under them
+void batch_report(const tr_batch *b, float ms, tr_batch_tuning *out) {
+    int bp = 1;
+    for (auto &I : b->inst) bp = I.A.bp > bp ? I.A.bp : bp;
+    out->bins_per_pass = b->knobs.bp;
+    out->waves_per_block = b->knobs.waves;
+    out->chunk = b->knobs.chunk;
+    out->sample_ms = ms;
+    out->widest_pass = bp;
+    out->waves_used = b->B.per_block;
+}
+
 void batch_drop_graph(tr_batch *b) {
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
@@ -1549,14 +1562,34 @@ extern "C" int tr_batch_tune(tr_batch *b, int sample_stride, tr_batch_tuning *be
     b->tuned_ms = cur_ms;
     rc = batch_capture(b);
     if (rc) return rc;
-    if (best) {
-        int bp = 1;
-        for (auto &I : b->inst) bp = I.A.bp > bp ? I.A.bp : bp;
-        best->bins_per_pass = bp;
-        best->waves_per_block = b->B.per_block;
-        best->chunk = b->B.chunk;
-        best->sample_ms = cur_ms;
+    if (best) batch_report(b, cur_ms, best);
+    return TR_OK;
+}
+
+extern "C" int tr_batch_set_tuning(tr_batch *b, const tr_batch_tuning *t) {
+    if (!b) return TR_EINVAL;
+    tr_ctx *ctx = b->ctx;
+    if (!t || t->bins_per_pass < 0 || t->waves_per_block < 0 || t->chunk < 0)
+        return tr_fail(ctx, TR_EINVAL, "tr_batch_set_tuning: negative setting");
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    Knobs k;
+    k.bp = t->bins_per_pass;
+    k.waves = t->waves_per_block;
+    k.chunk = t->chunk;
+    const Knobs old = b->knobs;
+    int rc = batch_configure(b, k);
+    if (rc) {
+        const std::string why = ctx->err;
+        if (batch_configure(b, old) == TR_OK) ctx->err = why; // the batch keeps its setting
+        return rc;
     }
+    b->tuned_ms = 0.0f;
+    return batch_capture(b);
+}
+
+extern "C" int tr_batch_get_tuning(const tr_batch *b, tr_batch_tuning *out) {
+    if (!b || !out) return TR_EINVAL;
+    batch_report(b, b->tuned_ms, out);
     return TR_OK;
 }
 

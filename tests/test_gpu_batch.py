@@ -84,7 +84,7 @@ def test_batch_graph_replays_match_oracle(lib, ctx, batch_setup):
             first = snap
         else:
             for a, c in zip(first, snap):
-                assert torch.allclose(a, c, rtol=1e-6, atol=0)
+                assert torch.equal(a, c)  # replays are bitwise reproducible
         # unrelated eager work on the same stream between replays
         t2, J2, F2, U2 = trace(ctx, _workload("turb32"))
         ctx.sync()
@@ -111,8 +111,9 @@ def test_batch_autotune_then_replay(lib, ctx, batch_setup):
     ws, trees, params, J, F, U, ref = batch_setup
     b = lib.Batch(ctx, trees, params, J, F, U)
     tun = b.tune(sample_stride=4)
-    say("tuned", tun.bins_per_pass, tun.waves_per_block, tun.chunk, tun.sample_ms)
-    assert 1 <= tun.bins_per_pass <= 16 and 1 <= tun.waves_per_block <= 16 and tun.chunk >= 1
+    say("tuned", tun.bins_per_pass, tun.waves_per_block, tun.chunk, tun.sample_ms, tun.widest_pass, tun.waves_used)
+    assert 0 <= tun.bins_per_pass <= 16 and 0 <= tun.waves_per_block <= 16 and tun.chunk >= 1
+    assert 1 <= tun.widest_pass <= 16 and 1 <= tun.waves_used <= 16
     assert tun.sample_ms > 0
     for x in J + F + U:
         x.fill_(-1.0)
@@ -120,6 +121,21 @@ def test_batch_autotune_then_replay(lib, ctx, batch_setup):
     ctx.sync()
     _check_all(ws, J, F, U, ref)
     b.free()
+    # the same setting applied to a new batch (a cached tuning): same configuration, no search
+    b2 = lib.Batch(ctx, trees, params, J, F, U)
+    b2.set_tuning(tun.bins_per_pass, tun.waves_per_block, tun.chunk)
+    got = b2.get_tuning()
+    assert (got.bins_per_pass, got.waves_per_block, got.chunk, got.widest_pass, got.waves_used) == \
+        (tun.bins_per_pass, tun.waves_per_block, tun.chunk, tun.widest_pass, tun.waves_used)
+    with pytest.raises(lib.TreerayError):
+        b2.set_tuning(-1, 0, 0)
+    assert b2.get_tuning().widest_pass == tun.widest_pass  # a rejected setting changes nothing
+    for x in J + F + U:
+        x.fill_(-1.0)
+    b2.launch()
+    ctx.sync()
+    _check_all(ws, J, F, U, ref)
+    b2.free()
 
 
 def test_batch_rejects_bad_input(lib, ctx, batch_setup):

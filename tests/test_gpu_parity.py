@@ -237,6 +237,29 @@ def test_trace_parity_merge_off_and_background(lib, ctx):
     _check_trace(J.cpu().numpy(), F.cpu().numpy().T, Jo, Fo)
 
 
+def test_trace_bitwise_reproducible(lib, ctx):
+    """Every target is traced by one wave whose additions into its bins run in program order,
+    so for a given pass width the result is the same bit for bit from run to run and under
+    any work split (targets per grab, waves per block).  A different pass width prunes other
+    subtrees per pass and changes the order of the sums, within the J bar."""
+    from paper_2204_09072_amd.run import trace, tree_of, upload
+    w = W.c2_turb64()
+    dev = upload(w)
+    tree = tree_of(ctx, w, dev)
+    runs = {}
+    for tag, kw in (("auto", {}), ("again", {}), ("chunk8", dict(chunk=8)), ("four_waves", dict(waves_per_block=4)),
+                    ("two_points", dict(bins_per_pass=2))):
+        say("reproducibility run", tag)
+        _, J, F, _ = trace(ctx, w, dev, tree=tree, **kw)
+        ctx.sync()
+        runs[tag] = (J.cpu().numpy().view(np.uint32).copy(), F.cpu().numpy().view(np.uint32).copy())
+    for tag in ("again", "chunk8", "four_waves"):
+        assert np.array_equal(runs[tag][0], runs["auto"][0]) and np.array_equal(runs[tag][1], runs["auto"][1]), tag
+    Ja, Jb = runs["auto"][0].view(np.float32), runs["two_points"][0].view(np.float32)
+    assert np.max(np.abs(Ja - Jb) / np.maximum(np.abs(Ja), 1e-30)) < 1e-5
+    tree.free()
+
+
 @pytest.mark.parametrize("name,n_sample,kernel", [("turb64", 1500, 0), ("core128", 160, 0),
                                                   ("core128", 80, 1), ("amr256", 400, 0)])
 def test_trace_parity_full_size_sampled(lib, ctx, name, n_sample, kernel):
@@ -487,3 +510,50 @@ def test_mlp_adam_steps_match_closed_form(lib, ctx):
         assert (err <= 1e-3 * lr + 1e-6 * np.abs(p)).all(), (step, err.max())
         assert np.abs(upd).max() > 0.5 * lr
     m.free()
+
+
+def test_mlp_checkpoint_resume(lib, ctx, tmp_path):
+    """Training state through a checkpoint file: parameters, Adam moments and step count
+    come back bit for bit, and a resumed network takes the same next Adam step (with the
+    restored step's bias correction) as the one that kept training."""
+    import torch
+    from paper_2204_09072_amd.guess import load_checkpoint, save_checkpoint
+    rng = np.random.default_rng(8)
+    norm = np.array([1, 2, 3, 0.5, 0.25, 2, -1, 3], np.float32)
+    a = lib.Mlp(ctx, lib.init_mlp_params(9), norm)
+    lr = 1e-2
+    batches = [(torch.from_numpy(rng.normal(size=(2000, 3)).astype(np.float32)).cuda(),
+                torch.from_numpy(rng.normal(size=2000).astype(np.float32)).cuda()) for _ in range(4)]
+    say("checkpoint: three steps, save, load")
+    for x, y in batches[:3]:
+        a.train_step(x, y, lr)
+    ctx.sync()
+    path = str(tmp_path / "guess.ckpt")
+    save_checkpoint(a, path)
+    b = load_checkpoint(ctx, path)
+    sa, sb = a.get_state(), b.get_state()
+    assert sa["steps"] == sb["steps"] == 3
+    for k in ("params", "adam_m", "adam_v", "norm"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert np.array_equal(sb["norm"], norm)
+    # forward passes agree exactly (same parameters, same bfloat16 rounding)
+    ya, yb = torch.zeros(2000, device="cuda"), torch.zeros(2000, device="cuda")
+    a.forward(batches[3][0], ya)
+    b.forward(batches[3][0], yb)
+    ctx.sync()
+    assert torch.equal(ya, yb)
+    # the fourth step on both; a restart at step 0 would move the parameters ~10x further
+    x, y = batches[3]
+    a.train_step(x, y, lr)
+    b.train_step(x, y, lr)
+    ctx.sync()
+    pa, pb = a.params().astype(np.float64), b.params().astype(np.float64)
+    assert (np.abs(pa - pb) <= 1e-3 * lr + 1e-6 * np.abs(pa)).all(), np.abs(pa - pb).max()
+    c = lib.Mlp(ctx, sa["params"], norm)  # same parameters, fresh Adam state
+    c.train_step(x, y, lr)
+    ctx.sync()
+    assert np.abs(c.params().astype(np.float64) - pa).max() > 10 * (1e-3 * lr)
+    with pytest.raises(lib.TreerayError):
+        b.set_state(sa["params"], None, None, -1)
+    for m in (a, b, c):
+        m.free()

@@ -44,10 +44,12 @@ def test_binding_structs_match_header(tmp_path):
 #include <stddef.h>
 #include "treeray.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(tr_grid), sizeof(tr_units), sizeof(tr_tree_info),
-         sizeof(tr_trace_params), sizeof(tr_dust_params), sizeof(tr_star));
-  printf("%zu %zu %zu %zu\n", offsetof(tr_grid, box_len), offsetof(tr_trace_params, j_bg),
-         offsetof(tr_dust_params, rel_tol), offsetof(tr_tree_info, u_len));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(tr_grid), sizeof(tr_units), sizeof(tr_tree_info),
+         sizeof(tr_trace_params), sizeof(tr_dust_params), sizeof(tr_star), sizeof(tr_batch_tuning),
+         sizeof(tr_uv_params));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(tr_grid, box_len), offsetof(tr_trace_params, j_bg),
+         offsetof(tr_dust_params, rel_tol), offsetof(tr_tree_info, u_len),
+         offsetof(tr_batch_tuning, waves_used));
   return 0;
 }
 '''
@@ -57,12 +59,13 @@ int main(void) {
         f.write(probe)
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
     out = subprocess.check_output([exe]).decode().split()
-    sizes = [int(v) for v in out[:6]]
-    offs = [int(v) for v in out[6:]]
+    sizes = [int(v) for v in out[:8]]
+    offs = [int(v) for v in out[8:]]
     assert sizes == [ctypes.sizeof(T.Grid), ctypes.sizeof(T.Units), ctypes.sizeof(T.TreeInfo),
-                     ctypes.sizeof(T.TraceParams), ctypes.sizeof(T.DustParams), 32]
+                     ctypes.sizeof(T.TraceParams), ctypes.sizeof(T.DustParams), 32,
+                     ctypes.sizeof(T.BatchTuning), ctypes.sizeof(T.UvParams)]
     assert offs == [T.Grid.box_len.offset, T.TraceParams.j_bg.offset, T.DustParams.rel_tol.offset,
-                    T.TreeInfo.u_len.offset]
+                    T.TreeInfo.u_len.offset, T.BatchTuning.waves_used.offset]
 
 
 def test_dense_block_layout_roundtrip():
@@ -89,3 +92,74 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_guess_checkpoint_file_roundtrip(tmp_path):
+    """The network's checkpoint files (flat float32 arrays + JSON header) read back exactly,
+    and a corrupted or foreign file is refused."""
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    import json
+    import paper_2204_09072_amd as T
+    from paper_2204_09072_amd.guess import read_checkpoint, write_checkpoint
+    rng = np.random.default_rng(3)
+    st = {"params": rng.normal(size=T.MLP_NPARAM).astype(np.float32),
+          "adam_m": rng.normal(size=T.MLP_NPARAM).astype(np.float32),
+          "adam_v": rng.random(T.MLP_NPARAM).astype(np.float32),
+          "steps": 1234, "norm": np.arange(8, dtype=np.float32)}
+    path = str(tmp_path / "net.ckpt")
+    write_checkpoint(path, st)
+    back = read_checkpoint(path)
+    for k in ("params", "adam_m", "adam_v", "norm"):
+        assert np.array_equal(back[k], st[k]), k
+    assert back["steps"] == 1234
+    assert os.path.getsize(path) == 3 * 4 * T.MLP_NPARAM
+    raw = bytearray(open(path, "rb").read())
+    raw[100] ^= 1
+    open(path, "wb").write(bytes(raw))
+    with pytest.raises(ValueError):
+        read_checkpoint(path)
+    write_checkpoint(path, st)
+    hdr = json.load(open(path + ".json"))
+    hdr["n_params"] = 17
+    json.dump(hdr, open(path + ".json", "w"))
+    with pytest.raises(ValueError):
+        read_checkpoint(path)
+
+
+def test_tuning_cache_store_and_key(tmp_path):
+    """The autotune cache keeps one setting per (architecture, N_side set, radial points,
+    instances, grid class) and applies a stored one instead of searching again."""
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from types import SimpleNamespace as NS
+    from paper_2204_09072_amd import tuning
+    trees = [NS(n_bins=21, n_cells=32768), NS(n_bins=29, n_cells=262144)]
+    params = [NS(n_side=4), NS(n_side=2)]
+    key = tuning.cache_key("gfx950:sramecc+:xnack-", trees, params)
+    assert key == "gfx950|n_side=2,4|n_bins=29|instances=2|cells~2^18"
+    path = str(tmp_path / "tune.json")
+    assert tuning.load(path) == {}
+
+    class FakeBatch:
+        def __init__(self):
+            self.searched = 0
+            self.applied = None
+
+        def tune(self, stride):
+            self.searched += 1
+            return NS(bins_per_pass=0, waves_per_block=8, chunk=2, sample_ms=1.25, widest_pass=14, waves_used=8)
+
+        def set_tuning(self, bp, waves, chunk):
+            self.applied = (bp, waves, chunk)
+
+        def get_tuning(self):
+            return NS(bins_per_pass=self.applied[0], waves_per_block=self.applied[1], chunk=self.applied[2])
+
+    b = FakeBatch()
+    t, hit = tuning.tune_cached(b, path, key)
+    assert not hit and b.searched == 1 and t.waves_per_block == 8
+    b2 = FakeBatch()
+    t2, hit2 = tuning.tune_cached(b2, path, key)
+    assert hit2 and b2.searched == 0 and b2.applied == (0, 8, 2)
+    assert tuning.load(path)[key]["widest_pass"] == 14
