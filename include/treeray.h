@@ -123,6 +123,9 @@ typedef struct tr_trace_params {
                               flip of axis a for bit a of o % 8), -1 = one drawn per target
                               cell from SplitMix64(orient_seed * 2^32 + cell) mod 48 */
     uint32_t orient_seed;
+    int32_t stack_limit;   /* test hook: ranges per wave walk stack; 0 = 56 depth + 8, which cannot
+                              overflow.  A smaller value (at least 9) can: the walk then drops
+                              subtrees, latches the overflow and tr_sync returns TR_EOVERFLOW */
 } tr_trace_params;
 
 /* Trace all cells of the tree: J (device float[n_cells], IRXE), F (device float[3][n],

@@ -51,7 +51,7 @@ class TraceParams(C.Structure):
                 ("cube_m", C.c_int32), ("merge", C.c_int32), ("j_bg", C.c_float),
                 ("bins_per_pass", C.c_int32), ("chunk", C.c_int32), ("waves_per_block", C.c_int32),
                 ("kernel", C.c_int32), ("per_node_kernel", C.c_int32), ("orientation", C.c_int32),
-                ("orient_seed", C.c_uint32)]
+                ("orient_seed", C.c_uint32), ("stack_limit", C.c_int32)]
 
 
 class BatchTuning(C.Structure):
@@ -259,14 +259,15 @@ def tree_export(ctx: Context, tree: Tree):
 
 def trace_params(n_side, theta=None, cube_m=0, merge=True, j_bg=0.0, bins_per_pass=0, chunk=0,
                  waves_per_block=0, kernel=0, per_node_kernel=False, orientation=0,
-                 orient_seed=0) -> TraceParams:
+                 orient_seed=0, stack_limit=0) -> TraceParams:
     """kernel: 0 automatic, 1 one wave per target (2, one block per target, is withdrawn).
     per_node_kernel: the 8-point kernel for every node instead of the table for far ones.
-    orientation: 0..47 signed axis permutation of the ray set, -1 drawn per target."""
+    orientation: 0..47 signed axis permutation of the ray set, -1 drawn per target.
+    stack_limit: test hook, a walk stack small enough to overflow (0 = one that cannot)."""
     th = (0, 0) if theta is None else theta
     return TraceParams(int(n_side), int(th[0]), int(th[1]), int(cube_m), int(bool(merge)),
                        float(j_bg), int(bins_per_pass), int(chunk), int(waves_per_block), int(kernel),
-                       int(bool(per_node_kernel)), int(orientation), int(orient_seed))
+                       int(bool(per_node_kernel)), int(orientation), int(orient_seed), int(stack_limit))
 
 
 def trace_rays(ctx: Context, tree: Tree, p: TraceParams, J, F, u_rad=None):

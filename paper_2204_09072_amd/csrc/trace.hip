@@ -1106,7 +1106,9 @@ int setup_instance(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, floa
     A.omega = (float)(4.0 * 3.14159265358979323846 / I.npix);
     A.j_bg = p->j_bg;
     A.c_light = (float)t->c_light;
+    if (p->stack_limit < 0) return tr_fail(ctx, TR_EINVAL, "stack_limit must be >= 0");
     A.kstack = stack_size(t->D);
+    if (p->stack_limit > 0 && p->stack_limit < A.kstack) A.kstack = p->stack_limit < 9 ? 9 : p->stack_limit;
     A.tab_slot = 0;
     if (p->orientation < -1 || p->orientation > 47)
         return tr_fail(ctx, TR_EINVAL, "orientation must be -1 (per target) or 0..47");

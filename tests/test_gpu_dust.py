@@ -158,3 +158,25 @@ def test_learned_one_kernel_equals_staged(lib, ctx):
     assert np.array_equal(out[False][0], out[True][0])
     assert np.array_equal(out[False][1], out[True][1])
     mlp.free()
+
+
+def test_poisoned_network_falls_back_to_the_bracket(lib, ctx):
+    """Failure recovery: a network whose output is NaN (NaN weights) or absurd (a huge
+    output bias) still gives every state its equilibrium temperature within 1e-5, since a
+    guess outside the bracket (or NaN) is clamped to it before Newton starts."""
+    import torch
+    from paper_2204_09072_amd.run import dust
+    s = W.dust_samples(20_000, seed=44).astype(np.float32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    To, _ = oracle.dust_eq(*[s[:, k].astype(np.float64) for k in range(3)], W.SIGMA_SB, W.C_LIGHT, 3.8e-33)
+    for tag, prm in (("nan", np.full(lib.MLP_NPARAM, np.nan, np.float32)),
+                     ("huge", np.concatenate([np.zeros(lib.MLP_NPARAM - 1), [1e4]]).astype(np.float32))):
+        say("poisoned network", tag)
+        m = lib.Mlp(ctx, prm)
+        for staged in (False, True):
+            T, it = dust(ctx, d(s[:, 0]), d(s[:, 1]), d(s[:, 2]), W.SIGMA_SB, W.C_LIGHT, mlp=m, staged=staged)
+            ctx.sync()
+            Tg = T.cpu().numpy()
+            assert np.isfinite(Tg).all(), (tag, staged)
+            assert np.max(np.abs(Tg - To) / To) < 1e-5, (tag, staged)
+        m.free()

@@ -557,3 +557,35 @@ def test_mlp_checkpoint_resume(lib, ctx, tmp_path):
         b.set_state(sa["params"], None, None, -1)
     for m in (a, b, c):
         m.free()
+
+
+def test_walk_stack_overflow_is_reported(lib, ctx):
+    """Failure detection: a walk stack too small for the tree (the stack_limit test hook)
+    makes the walk drop subtrees, latch the overflow and tr_sync report TR_EOVERFLOW, for the
+    trace and for the walk counters; the flag is then clear and a normal trace matches the
+    oracle again.  The kernel itself never writes past its stack (pushes beyond it are
+    dropped), so the condition is forced without any out-of-bounds access."""
+    import torch
+    from paper_2204_09072_amd.run import trace, tree_of, upload
+    w = TREE_CASES["turb32"]()
+    dev = upload(w)
+    tree = tree_of(ctx, w, dev)
+    say("stack overflow forced: trace")
+    trace(ctx, w, dev, tree=tree, stack_limit=9)
+    with pytest.raises(lib.TreerayError) as e:
+        ctx.sync()
+    assert e.value.code == lib.TR_EOVERFLOW
+    say("stack overflow forced: walk counts")
+    cnt = torch.zeros((tree.n_cells, 3), dtype=torch.int32, device="cuda")
+    lib.walk_counts(ctx, tree, lib.trace_params(w.n_side, theta=w.theta, stack_limit=9), cnt)
+    with pytest.raises(lib.TreerayError) as e:
+        ctx.sync()
+    assert e.value.code == lib.TR_EOVERFLOW
+    with pytest.raises(lib.TreerayError):
+        trace(ctx, w, dev, tree=tree, stack_limit=-1)
+    say("normal trace after the overflow")
+    _, J, F, _ = trace(ctx, w, dev, tree=tree)
+    ctx.sync()
+    Jo, Fo = oracle.Tree(w).trace(oracle.params(w.n_side, theta=w.theta))
+    _check_trace(J.cpu().numpy(), F.cpu().numpy().T, Jo, Fo)
+    tree.free()
