@@ -615,6 +615,10 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     const int tx = __builtin_amdgcn_readfirstlane(tr.x & 0xffff), ty = __builtin_amdgcn_readfirstlane(tr.y & 0xffff),
               tz = __builtin_amdgcn_readfirstlane(tr.z);
     const int4 c256 = make_int4(tx * TR_FX, ty * TR_FX, tz * TR_FX, 0);
+    // copies in vector registers for the walk's per-lane differences and comparisons: as
+    // scalars they outnumber the scalar registers and come back from spill lanes every step
+    int wtx = tx, wty = ty, wtz = tz, wtid = tid;
+    asm volatile("" : "+v"(wtx), "+v"(wty), "+v"(wtz), "+v"(wtid));
     const int orient = __builtin_amdgcn_readfirstlane(target_orient(A.orient, A.orient_seed, A.leaf_cell[tid]));
     RayState<NSLOT> R;
 #pragma unroll
@@ -644,6 +648,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
         }
         if (lane == 0) stk[0] = 0u; // the root: first node 0, one node
         int sp = 1, qf = 0, qs = 0; // stack depth, far and near queue lengths
+        bool ovf = false;
         wave_sync();
         for (;;) {
             // The three counts are the same on every lane (they change only by ballot
@@ -653,7 +658,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
             sp = __builtin_amdgcn_readfirstlane(sp);
             qf = __builtin_amdgcn_readfirstlane(qf);
             qs = __builtin_amdgcn_readfirstlane(qs);
-            if (sp <= 0 && qf <= 0 && qs <= 0) break;
+            if ((sp | qf | qs) == 0) break; // all three are >= 0
             if (sp > 0) {
                 const int npop = sp < 8 ? sp : 8;
                 const int r = lane >> 3, k = lane & 7;
@@ -677,16 +682,16 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                     const bool leaf = (nd.x >> 20) & 1;
                     const bool thick = (nd.x >> 21) & 1;
                     const int s = A.root_edge >> depth;
-                    const int vx = (nd.x & 0xffff) - tx, vy = (nd.y & 0xffff) - ty, vz = nd.z - tz;
+                    const int vx = (nd.x & 0xffff) - wtx, vy = (nd.y & 0xffff) - wty, vz = nd.z - wtz;
                     // |v| < 2^12, s < 2^12: d2 and s^2 fit 24 bits
                     const int d2 = __mul24(vx, vx) + __mul24(vy, vy) + __mul24(vz, vz);
                     const int s2 = __mul24(s, s);
                     const bool accept = A.wide_open ? (int64_t)s2 * A.th_den2 < (int64_t)A.th_num2 * d2
                                                     : __umul24(s2, A.th_den2) < __umul24(A.th_num2, d2);
                     // (bitwise rather than short-circuit operators: no branches)
-                    const bool acc = valid & (leaf ? nid != tid : accept); // leaves always, but the target
+                    const bool acc = valid & (leaf ? nid != wtid : accept); // leaves always, but the target
                     const bool opn = valid & !leaf & !accept;
-                    n_b += (valid & leaf & (nid != tid)) ? 1 : 0;
+                    n_b += (valid & leaf & (nid != wtid)) ? 1 : 0;
                     n_h += (valid & !leaf & accept) ? 1 : 0;
                     n_open += opn ? 1 : 0;
                     const int ext = (acc & thick & (A.merge != 0)) ? (s >> 1) : 0;
@@ -746,12 +751,9 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                 const int pos = __builtin_popcountll(bal & below);
                 const int npush = __builtin_popcountll(bal);
                 if (open && sp + pos < A.kstack) stk[sp + pos] = push;
-                if (sp + npush > A.kstack) {
-                    if (lane == 0) atomicOr(A.err, 4);
-                    sp = A.kstack;
-                } else {
-                    sp += npush;
-                }
+                // an overflow drops the pushes past the stack and is reported once per pass
+                ovf |= sp + npush > A.kstack;
+                sp = min(sp + npush, A.kstack);
                 if (!COUNT) {
                     const uint64_t fb = __ballot(enq && far1), gb = __ballot(enq && !far1);
                     if (enq) {
@@ -788,6 +790,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                 wave_sync();
             }
         }
+        if (ovf && lane == 0) atomicOr(A.err, 4);
         if (COUNT) break;
         // the thick accumulators' atomics of every lane have been performed at the device
         // cache before any lane reads them back
