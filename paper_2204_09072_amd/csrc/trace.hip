@@ -31,12 +31,10 @@ constexpr float kPiF = 3.14159265358979f;
 // 0, the near-node one down from kQueue - 1; each holds < 64 entries before a walk step
 // adds at most 64
 constexpr int kQueue = 192;
-// far-node entries also carry their offset from the target (positions < 128)
-constexpr int kFarQ = 128;
 constexpr int kFields = 6;  // L_thin, A_thin, L_thick*V, A_thick, V_thick, Q
 constexpr int kThin = 2;    // fields held in LDS: L_thin, A_thin
-constexpr int kMaxBp = 16;  // segments per pass: merge flags in bits 0-15 of a ray's flag
-                            // word, thick-content flags in bits 16-31
+constexpr int kMaxBp = 16;  // segments per pass: a ray's merge and thick-content flags take
+                            // 2 kMaxBp bits (flag_words)
 
 // ranges on a wave's walk stack: each step pops up to 8 ranges and pushes at most 64,
 // so at most 56 per level of the tree stay behind
@@ -85,8 +83,13 @@ struct TraceArgs {
 };
 
 struct LdsLayout {
-    int bins, flg, stk, qnode, qpk, qmeta, total;
+    int bins, flg, stk, qnode, qpk, total;
 };
+
+// Merge and thick-content flags of a pass, per ray: bit k (merge segment k with the next)
+// and bit tsh + k (segment k holds thick content), k relative to the pass.  With at most 8
+// segments per pass they take 16 bits and two rays share a word (ray h in half h & 1).
+__host__ __device__ inline int flag_words(int npix, int bp) { return bp <= 8 ? (npix + 1) >> 1 : npix; }
 
 __host__ __device__ inline LdsLayout lds_layout(int npix, int bp, int kstack, bool count) {
     LdsLayout L;
@@ -94,15 +97,13 @@ __host__ __device__ inline LdsLayout lds_layout(int npix, int bp, int kstack, bo
     L.bins = o;
     o += count ? 0 : npix * bp * kThin * 4;
     L.flg = o;
-    o += count ? 0 : npix * 4;
+    o += count ? 0 : flag_words(npix, bp) * 4;
     L.stk = o;
     o += kstack * 4;
     L.qnode = o;
     o += count ? 0 : kQueue * 4;
     L.qpk = o;
     o += count ? 0 : kQueue * 4;
-    L.qmeta = o;
-    o += count ? 0 : kFarQ * 12;
     L.total = (o + 15) & ~15;
     return L;
 }
@@ -362,17 +363,15 @@ __device__ __forceinline__ float beta_of(int dx, int dy, int dz, int i) {
 // depth << 19 | thick content << 23 | distance class << 24 (far nodes, at most kAlphaMax).
 //
 // Map queued nodes (Sec. 4.2.1/4.2.2): one lane per node, one LDS update per distinct pixel.
-// FAR: every node of the batch is at least 8 edges away and takes the tabulated kernel; its
-// queue entry brings the node's offset from the walk, so the mapping position is not read
-// again and the node's sums and its table entry are fetched side by side.  Otherwise the per-node kernel: the node
-// cube's 2x2x2 sub-points, each binned to a direction cell and its pixel, sorted to find
-// the distinct pixels.  Merge flags and thick-content flags share one word per ray in flg
-// (thick bits from bit 16).
+// FAR: every node of the batch is at least 8 edges away and takes the tabulated kernel,
+// keyed by the direction cell and distance class of its offset, which every lane computes
+// from the node's mapping position.  Otherwise the per-node kernel: the node cube's 2x2x2
+// sub-points, each binned to a direction cell and its pixel, sorted to find the distinct
+// pixels.  Merge and thick-content flags go to the rays' flag words (flag_words).
 template <bool LDS_TABLE, bool FAR>
 __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid, const int *qnode, const uint32_t *qpk,
                                           int pass_a, int4 c256, int orient, const uint8_t *tab8, float *bins,
-                                          uint32_t *flg, float4 *thick, const int *qdx = nullptr, const int *qdy = nullptr,
-                                          const int *qdz = nullptr) {
+                                          uint32_t *flg, float4 *thick) {
     uint32_t starts = 0;
     int pix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     float Lt = 0, At = 0, LVk = 0, Ak = 0, Vk = 0, beta = 0;
@@ -399,8 +398,11 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
         float vkh;
         int dx = 0, dy = 0, dz = 0;
         if (FAR) {
-            // the walk's offset: table key and radial kernel here, with every lane busy
-            dx = qdx[ev]; dy = qdy[ev]; dz = qdz[ev];
+            // the node's offset from its mapping position: table key and radial kernel here,
+            // with every lane busy
+            const int4 p = at32(A.pcol, node);
+            vkh = __int_as_float(p.w);
+            dx = p.x - c256.x; dy = p.y - c256.y; dz = p.z - c256.z;
             beta = beta_of(dx, dy, dz, (seg > 0 ? seg : 0) + pass_a);
             const int key = alpha_key(dx, dy, dz, (int)(pk >> 24), orient, A.log2m, A.alpha_c1);
             // both reads, the one not needed at a harmless index, instead of a branch
@@ -408,8 +410,6 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
             const int ok = lookup(key < 0 ? -1 - key : 0);
             en = key < 0 ? 0ull : ek;
             own = key < 0 ? ok : -1;
-            vkh = 0.0f;
-            if (!leaf && ((pk >> 23) & 1u)) vkh = __int_as_float(A.pcol[node].w); // thick h-node (rare)
         } else {
             const int4 p = at32(A.pcol, node);
             vkh = __int_as_float(p.w);
@@ -482,8 +482,9 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
             ft = 1u << seg;
         }
         const uint32_t fm = on ? fbits : 0u;
-        const uint32_t fl = fm | (ft << 16);
-        if (fl) atomicOr(flg + px, fl);
+        const bool half = A.bp <= 8;
+        const uint32_t fl = fm | (ft << (half ? 8 : 16));
+        if (fl) atomicOr(flg + (half ? px >> 1 : px), half ? fl << ((px & 1) << 4) : fl);
     };
     auto flush = [&](int key, float v0, float v1) {
         // runs of equal keys within rows of 16 lanes (wave-uniform control flow): run id =
@@ -606,8 +607,6 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     uint32_t *stk = reinterpret_cast<uint32_t *>(lds + LL.stk);
     int *qnode = reinterpret_cast<int *>(lds + LL.qnode);
     uint32_t *qpk = reinterpret_cast<uint32_t *>(lds + LL.qpk);
-    int *qdx = reinterpret_cast<int *>(lds + LL.qmeta);
-    int *qdy = qdx + kFarQ, *qdz = qdy + kFarQ;
     const int lane = lane_id();
     // the target's values are the same on every lane: held in scalar registers
     const int tid = __builtin_amdgcn_readfirstlane(A.targets[ti]);
@@ -644,7 +643,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
         if (!COUNT) {
             const int nf = A.npix * A.bp * kThin;
             for (int k = lane; k < nf; k += 64) bins[k] = 0.0f;
-            for (int k = lane; k < A.npix; k += 64) flg[k] = 0u;
+            for (int k = lane; k < flag_words(A.npix, A.bp); k += 64) flg[k] = 0u;
         }
         if (lane == 0) stk[0] = 0u; // the root: first node 0, one node
         int sp = 1, qf = 0, qs = 0; // stack depth, far and near queue lengths
@@ -668,7 +667,6 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                 const int node = (r < npop && k <= (int)(rg & 7u)) ? (int)(rg >> 3) + k : -1;
                 bool open, enq = false, far1 = false;
                 uint32_t push, pk = 0;
-                int fdx = 0, fdy = 0, fdz = 0;
                 {
                     // Every lane takes the same steps and selects by its node's kind instead
                     // of branching (a lane without a node reads the root and keeps nothing).
@@ -743,7 +741,6 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                              ((uint32_t)h.k1 << 12) | ((leaf ? 1u : 0u) << 18) | ((uint32_t)depth << 19) |
                              ((thick ? 1u : 0u) << 23) |
                              (far1 ? (uint32_t)(c < kAlphaMax ? c : kAlphaMax) << 24 : 0u);
-                        fdx = dx; fdy = dy; fdz = dz;
                     }
                 }
                 const uint64_t below = (1ull << lane) - 1ull;
@@ -761,11 +758,6 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                                              : kQueue - 1 - qs - __builtin_popcountll(gb & below);
                         qnode[qp] = node;
                         qpk[qp] = pk;
-                        if (far1) {
-                            qdx[qp] = fdx;
-                            qdy[qp] = fdy;
-                            qdz[qp] = fdz;
-                        }
                     }
                     qf += __builtin_popcountll(fb);
                     qs += __builtin_popcountll(gb);
@@ -777,8 +769,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
             if (qf >= 64 || (sp == 0 && qf > 0)) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = qf - nq + (lane < nq ? lane : 0);
-                map_queue<LDS_TABLE, true>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick, qdx,
-                                           qdy, qdz);
+                map_queue<LDS_TABLE, true>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick);
                 qf -= nq;
                 wave_sync();
             }
@@ -800,7 +791,9 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
         for (int sl = 0; sl < NSLOT; ++sl) {
             const int h = lane + 64 * sl;
             if (h >= A.npix) continue;
-            const uint32_t fl = flg[h];
+            const bool half = A.bp <= 8;
+            const uint32_t fl = half ? (flg[h >> 1] >> ((h & 1) << 4)) & 0xffffu : flg[h];
+            const int tsh = half ? 8 : 16;
             float4 *carry = thick + A.npix * A.bp + 2 * h;
             float acc[kFields] = {0, 0, 0, 0, 0, 0};
             if (R.run_i[sl] != 0) {
@@ -814,7 +807,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
             for (int i = P.a; i < P.b; ++i) {
                 const float *th = bins + (h * A.bp + (i - P.a)) * kThin;
                 float v[kFields] = {th[0], th[1], 0.0f, 0.0f, 0.0f, 0.0f};
-                if ((fl >> (16 + i - P.a)) & 1u) {
+                if ((fl >> (tsh + i - P.a)) & 1u) {
                     // read and clear the segment's thick content
                     float *tk = reinterpret_cast<float *>(thick + h * A.bp + (i - P.a));
 #pragma unroll
@@ -1049,11 +1042,12 @@ int table_bytes(int M) { return (6 * M * M + 15) & ~15; }
 int max_waves_for(int npix) { return npix > 192 ? 4 : 16; } // the kernel's launch bound
 // waves a CU should hold at once; passes are sized so that this many waves share the CU's
 // LDS.  Wide rays (~190 VGPRs, two waves per SIMD): 8 (128^3 core, 2 segments per pass and
-// 8 waves 13.6 s, 4 and 4 waves 23.3 s).  Otherwise 16 for batches; a single tree takes 15:
-// on the 128^3 core the same 3 segments per pass as for 16 (and 16 waves still fit), on the
-// deeper AMR tree 3 instead of 2 (2.12 s against 2.19 s), while the 64-instance batch ran
-// 2 % slower with 15.
-int waves_cu_for(int npix, bool single = false) { return npix > 192 ? 8 : (single ? 15 : 16); }
+// 8 waves 13.6 s, 4 and 4 waves 23.3 s).  Otherwise 16, four per SIMD, the most the
+// registers allow.  Each pass re-walks the tree, so the LDS left beside the bins decides
+// the walk's cost: with two rays per flag word and no far-node offsets in the queue, the
+// 128^3 core and the AMR 256^3-equivalent tree take 4 segments per pass at 16 waves (1.39 s
+// and 1.91 s, against 1.42 s and 2.00 s with 3).
+int waves_cu_for(int npix) { return npix > 192 ? 8 : 16; }
 int nslot_for(int npix) { return npix <= 64 ? 1 : (npix <= 192 ? 3 : 12); }
 // the one-wave kernels keep the pixel table in LDS for up to 64 rays (N_side <= 2, at most
 // 6 KB); beyond that only near nodes read it, from global memory, and the LDS holds more
@@ -1169,7 +1163,7 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     const bool tab_lds = !count && table_in_lds(npix);
     const int lds_table = tab_lds ? table_bytes(I.M) : 0;
     const int max_waves = max_waves_for(npix);
-    set_bp(I, choose_bp(I, p->bins_per_pass, lds_table, waves_cu_for(npix, true), count), count);
+    set_bp(I, choose_bp(I, p->bins_per_pass, lds_table, waves_cu_for(npix), count), count);
     TraceArgs &A = I.A;
     A.chunk = p->chunk > 0 ? p->chunk : 1; // one target per grab: a short tail (128^3 core: 1.59 s, 1.61 s with 4)
     A.lds_table = lds_table;
