@@ -341,8 +341,9 @@ def traffic_probe(name):
 
 
 def mlp_probe(n=2_097_152, steps=20, reps=3):
-    """Guess-network inference (k_mlp_infer) followed by the learned-start solve on n
-    log-uniform interior states, `reps` times, then `steps` training steps of 8192 samples
+    """The learned-start solve on n log-uniform interior states, `reps` times in one kernel
+    (k_dust_learned: inference and Newton together) and `reps` times staged (k_mlp_infer,
+    then k_dust from the stored guesses), then `steps` training steps of 8192 samples
     (k_mlp_train + k_adam): for rocprofv3 runs of the matrix-core counters."""
     import torch
     import paper_2204_09072_amd as T
@@ -354,16 +355,17 @@ def mlp_probe(n=2_097_152, steps=20, reps=3):
     norm = np.array([*f.mean(0), *(1.0 / f.std(0)), 1.3, 2.0], np.float32)
     mlp = T.Mlp(ctx, T.init_mlp_params(0), norm)
     out = torch.empty(n, device="cuda")
-    dp = T.dust_params(W.SIGMA_SB, W.C_LIGHT)
-    for _ in range(reps):
-        T.dust_equilibrium(ctx, r, u, t, dp, out, None, mlp)
+    for staged in (False, True):
+        dp = T.dust_params(W.SIGMA_SB, W.C_LIGHT, staged=staged)
+        for _ in range(reps):
+            T.dust_equilibrium(ctx, r, u, t, dp, out, None, mlp)
     rng = np.random.default_rng(5)
     x = torch.from_numpy(rng.normal(size=(8192, 3)).astype(np.float32)).cuda()
     y = torch.from_numpy(rng.normal(size=8192).astype(np.float32)).cuda()
     for _ in range(steps):
         mlp.train_step(x, y, 1e-3)
     ctx.sync()
-    log(f"mlp probe: {reps} inferences of {n} states, {steps} training steps of 8192")
+    log(f"mlp probe: {reps} fused and {reps} staged learned solves of {n} states, {steps} training steps of 8192")
     mlp.free()
 
 
