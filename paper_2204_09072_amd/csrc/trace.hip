@@ -696,7 +696,8 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                     // One box test serves both kinds of node (a lane is opened or accepted, not
                     // both), in lattice units with R_i = i^2:
                     //  - an opened h-node keeps its subtree when r_max + s/4 >= R_a and
-                    //    r_min - s/4 < R_b, with r over the node cube (half edge s/2);
+                    //    r_min - s/4 < R_b, with r over the node cube (half edge s/2) and the
+                    //    s/4 only when the subtree holds thick content to be merged;
                     //  - an accepted node can reach the pass when r_max >= R_a and r_min < R_b:
                     //    its mapping position lies in its cube (a leaf's is its centre, half
                     //    edge 0), and thick material reaches a further s/2 for the merge flags.
@@ -709,7 +710,9 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                     const int rmax2 = __mul24(fx, fx) + __mul24(fy, fy) + __mul24(fz, fz);
                     bool keep = true;
                     if (!COUNT) {
-                        const int q4 = s >> 2;
+                        // the s/4 margin covers the merge extents of thick descendants; a
+                        // subtree without thick content keeps exactly its cube's range
+                        const int q4 = (thick & (A.merge != 0)) ? s >> 2 : 0;
                         const int lo = lo_cut - q4, hi = hi_cut + q4;
                         keep = !((lo > 0) & (rmax2 < __mul24(lo, lo))) & (last | (rmin2 < __mul24(hi, hi)));
                     }
