@@ -64,7 +64,8 @@ typedef struct tr_units {
     double c;     /* speed of light */
 } tr_units;
 
-/* point source with non-ionising luminosity L_IR (Sec. 4.1.1); host array */
+/* point source with non-ionising luminosity L_IR (Sec. 4.1.1); a host array for
+ * tr_build_tree, a device array for tr_tree_refill */
 typedef struct tr_star {
     double x, y, z, L;
 } tr_star;
@@ -79,6 +80,14 @@ int tr_build_tree(tr_ctx *ctx, const tr_grid *grid, const float *rho, const floa
                   const float *t_dust, const tr_star *stars, int n_stars,
                   const tr_units *units, tr_tree **out);
 void tr_tree_free(tr_tree *tree);
+/* Refill a tree's content for new cell fields and stars on the same blocks (Sec. 4.1.1 b-nodes,
+ * App. A h-nodes and centres of luminosity): the same node arrays as tr_build_tree of the same
+ * grid with these inputs, bit for bit, without allocating or synchronising, so it can be
+ * captured in a graph with the calls that follow it.  rho, kappa (or NULL), t_dust as in
+ * tr_build_tree; stars: DEVICE array of n_stars tr_star (NULL when n_stars = 0).  The units
+ * are the build's; no input validation.  Asynchronous. */
+int tr_tree_refill(tr_ctx *ctx, tr_tree *tree, const float *rho, const float *kappa,
+                   const float *t_dust, const tr_star *stars, int n_stars);
 
 typedef struct tr_tree_info {
     int64_t n_node, n_leaf, n_cells;

@@ -86,6 +86,7 @@ _sig("tr_last_error", C.c_char_p, [_P])
 _sig("tr_sync", _I, [_P])
 _sig("tr_build_tree", _I, [_P, C.POINTER(Grid), _P, _P, _P, _P, _I, C.POINTER(Units), C.POINTER(_P)])
 _sig("tr_tree_free", None, [_P])
+_sig("tr_tree_refill", _I, [_P, _P, _P, _P, _P, _P, _I])
 _sig("tr_tree_get_info", _I, [_P, C.POINTER(TreeInfo)])
 _sig("tr_tree_export", _I, [_P, _P, _P, _P, _P, _P, _P, _P])
 _sig("tr_trace_rays", _I, [_P, _P, C.POINTER(TraceParams), _P, _P, _P])
@@ -182,6 +183,13 @@ class Tree:
         self.root_edge = info.root_edge
         self.n_bins = info.n_bins
         self.u_len = info.u_len
+
+    def refill(self, rho, kappa, t_dust, stars=None):
+        """tr_tree_refill: new cell fields (device float32) and stars (device float64 [n, 4]
+        or None) on the same blocks; asynchronous, allocation-free."""
+        n = 0 if stars is None else int(stars.shape[0])
+        self.ctx.check(_lib.tr_tree_refill(self.ctx.h, self.h, _ptr(rho), _ptr(kappa), _ptr(t_dust),
+                                           _ptr(stars) if n else None, n))
 
     def free(self, _free=_lib.tr_tree_free):
         if getattr(self, "h", None):

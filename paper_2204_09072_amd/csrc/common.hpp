@@ -72,6 +72,10 @@ struct tr_tree {
     float *cell_tau = nullptr;    // rho kappa dx
     float *cell_kappa = nullptr;
     float *cell_src = nullptr;    // hosted star luminosity / u_len^2 (0 if none)
+    // kept for tr_tree_refill: the FP64 sums of the up-sweep (L_thin, LV_thick, A_thin,
+    // A_thick, V_thick, centre-of-luminosity weight; n_node each) and the per-cell star light
+    double *s64[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double *src = nullptr;
 };
 
 int tr_fail(tr_ctx *ctx, int code, const char *fmt, ...);

@@ -52,10 +52,20 @@ extern "C" int tr_dust_fixed_point(tr_ctx *ctx, const tr_grid *grid, const float
     int rc = TR_OK, it = 0;
     float change = 0.0f;
     const int blocks = (int)(tr_div_up(n, 256) < 4096 ? tr_div_up(n, 256) : 4096);
+    // the tree is built once; each later sweep refills its content for the new dust
+    // temperature (kappa = kappa_P(T_dust)) on the same blocks, without allocating
+    tr_tree *tree = nullptr;
+    tr_star *d_stars = nullptr;
+    if (n_stars > 0 && (hipMalloc(&d_stars, sizeof(tr_star) * n_stars) != hipSuccess ||
+                        hipMemcpyAsync(d_stars, stars, sizeof(tr_star) * n_stars, hipMemcpyHostToDevice,
+                                       ctx->stream) != hipSuccess)) {
+        hipFree(d_stars);
+        hipFree(t_new);
+        return tr_fail(ctx, TR_ENOMEM, "fixed point star buffer");
+    }
     for (it = 1; it <= max_iter; ++it) {
-        tr_tree *tree = nullptr;
-        // opacity and emission of the current dust temperature (kappa = kappa_P(T_dust))
-        rc = tr_build_tree(ctx, grid, rho, nullptr, t_dust, stars, n_stars, units, &tree);
+        rc = it == 1 ? tr_build_tree(ctx, grid, rho, nullptr, t_dust, stars, n_stars, units, &tree)
+                     : tr_tree_refill(ctx, tree, rho, nullptr, t_dust, d_stars, n_stars);
         if (rc) break;
         rc = tr_trace_rays(ctx, tree, tp, J, F, u_rad);
         if (rc == TR_OK) rc = tr_dust_equilibrium(ctx, n, rho, u_rad, t_gas, dp, mlp, t_new, nullptr);
@@ -72,10 +82,11 @@ extern "C" int tr_dust_fixed_point(tr_ctx *ctx, const tr_grid *grid, const float
             memcpy(&change, &bits, sizeof(float));
         }
         if (rc == TR_OK) rc = tr_sync(ctx); // device-side failures of the trace
-        tr_tree_free(tree);
         if (rc || change <= tol) break;
     }
     hipStreamSynchronize(ctx->stream);
+    tr_tree_free(tree);
+    hipFree(d_stars);
     hipFree(t_new);
     if (iterations) *iterations = it > max_iter ? max_iter : it;
     if (max_rel_change) *max_rel_change = change;

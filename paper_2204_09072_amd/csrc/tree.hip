@@ -127,33 +127,45 @@ __global__ void k_cells(const int4 *__restrict__ blocks, int64_t n_cells, int D,
     leaf_cell[id] = (int32_t)c;
 }
 
-// Stars in input order, one thread: the per-cell sum then has a fixed order.
-__global__ void k_stars(const double4 *__restrict__ stars, int n_star, int D, int max_level,
-                        int64_t n_fine, double x0, double y0, double z0, double dxmin, double u2,
-                        DenseLayout L, const uint32_t *__restrict__ occ, const int *__restrict__ ids,
-                        const int32_t *__restrict__ leaf_cell, double *__restrict__ src) {
+// Stars in input order, one thread: the per-cell sum then has a fixed order.  A star's host
+// cell is the leaf holding its fine cell floor((x - x0) / dx_min) (half-open, clamped to the
+// grid), found by descending from the root: at each node the octant of the fine cell's
+// centre 2 f + 1 (in u) against the node's centre, then that child among the existing ones.
+__global__ void k_stars(const double4 *__restrict__ stars, int n_star, int64_t n_fine, double x0,
+                        double y0, double z0, double dxmin, double u2, const int4 *__restrict__ geo,
+                        const uint32_t *__restrict__ meta, const int32_t *__restrict__ leaf_cell,
+                        double *__restrict__ src) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     for (int s = 0; s < n_star; ++s) {
         double4 st = stars[s];
         double pos[3] = {st.x - x0, st.y - y0, st.z - z0};
-        int64_t f[3];
+        int64_t c[3];
         for (int a = 0; a < 3; ++a) {
             double q = floor(pos[a] / dxmin);
             if (q < 0) q = 0;
             if (q > (double)(n_fine - 1)) q = (double)(n_fine - 1);
-            f[a] = (int64_t)q;
+            c[a] = 2 * (int64_t)q + 1;
         }
-        for (int lev = max_level; lev >= 0; --lev) {
-            int sh = max_level - lev, dc = D - sh;
-            int64_t e = L.base[dc] + morton((uint32_t)(f[0] >> sh), (uint32_t)(f[1] >> sh),
-                                            (uint32_t)(f[2] >> sh));
-            if (occ[e] & 2u) {
-                int cell = leaf_cell[ids[e]];
+        int id = 0;
+        for (;;) {
+            const uint32_t m = meta[id];
+            if (m & (1u << 12)) {
+                const int cell = leaf_cell[id];
                 src[cell] = src[cell] + st.w / u2;
                 break;
             }
+            const int4 g = geo[id];
+            const uint32_t k = (c[0] > g.x ? 1u : 0u) | (c[1] > g.y ? 2u : 0u) | (c[2] > g.z ? 4u : 0u);
+            const uint32_t mask = (m >> 4) & 255u;
+            if (!((mask >> k) & 1u)) break; // no such child: the grid does not cover the star
+            id = g.w + __builtin_popcount(mask & ((1u << k) - 1u));
         }
     }
+}
+
+__global__ void k_zero_f64(double *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
 }
 
 struct Scratch64 {
@@ -202,8 +214,8 @@ __global__ void k_leaf_fill(int64_t n_cells, const float *__restrict__ rho,
         S64.Vk[id] = V;
         S64.xi[id] = La * (e * e) + Sv;
         o.x = copysignf((float)La, -1.0f);
-        meta[id] |= 1u << 13; // thick content
     }
+    meta[id] = (meta[id] & ~(1u << 13)) | (tau < 1.0 ? 0u : 1u << 13); // thick content
     o.y = (float)A;
     o.z = (float)Sv;
     o.w = 0.0f;
@@ -259,7 +271,7 @@ __global__ void k_up(int64_t lo, int64_t hi, const int4 *__restrict__ geo,
     pcol[id] = p;
     q[id] = make_float4((float)Lt, (float)LVk, (float)At, (float)Ak);
     vthick[id] = (float)Vk;
-    if (Vk > 0.0) meta[id] = mt | (1u << 13); // thick content
+    meta[id] = (mt & ~(1u << 13)) | (Vk > 0.0 ? 1u << 13 : 0u); // thick content
 }
 
 // Walk record of every node, one 16-byte load per visit:
@@ -290,6 +302,8 @@ extern "C" void tr_tree_free(tr_tree *t) {
     hipFree(t->packed);
     hipFree(t->leaf_cell); hipFree(t->node_of_cell); hipFree(t->targets);
     hipFree(t->cell_tau); hipFree(t->cell_kappa); hipFree(t->cell_src);
+    for (double *p : t->s64) hipFree(p);
+    hipFree(t->src);
     delete t;
 }
 
@@ -456,8 +470,8 @@ extern "C" int tr_build_tree(tr_ctx *ctx, const tr_grid *grid, const float *rho,
             cleanup(); return tr_fail(ctx, TR_EHIP, "star upload failed");
         }
         double dxmin = grid->box_len / (double)n_fine;
-        k_stars<<<1, 64, 0, st>>>(d_stars, n_stars, D, t->max_level, n_fine, grid->x0[0], grid->x0[1],
-                                  grid->x0[2], dxmin, t->u_len * t->u_len, L, occ, ids, t->leaf_cell, src);
+        k_stars<<<1, 64, 0, st>>>(d_stars, n_stars, n_fine, grid->x0[0], grid->x0[1], grid->x0[2], dxmin,
+                                  t->u_len * t->u_len, t->geo, t->meta, t->leaf_cell, src);
     }
     k_leaf_fill<<<tr_div_up(nc, TPB), TPB, 0, st>>>(nc, rho, kappa, t_dust, src, t->node_of_cell, t->meta,
                                                     t->root_edge, t->u_len, units->sigma, S64, t->q,
@@ -472,10 +486,43 @@ extern "C" int tr_build_tree(tr_ctx *ctx, const tr_grid *grid, const float *rho,
         cleanup(); return tr_fail(ctx, TR_EHIP, "tree kernels failed");
     }
     tr_tree *res = t;
-    t = nullptr; // keep the tree, free the temporaries
+    t = nullptr; // keep the tree (with its FP64 sums and star light, for refills), free the rest
+    res->s64[0] = S64.Lt; res->s64[1] = S64.LVk; res->s64[2] = S64.At;
+    res->s64[3] = S64.Ak; res->s64[4] = S64.Vk; res->s64[5] = S64.xi;
+    res->src = src;
+    S64 = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    src = nullptr;
     cleanup();
     *out = res;
     return TR_OK;
+}
+
+extern "C" int tr_tree_refill(tr_ctx *ctx, tr_tree *t, const float *rho, const float *kappa,
+                              const float *t_dust, const tr_star *stars, int n_stars) {
+    if (!ctx) return TR_EINVAL;
+    if (!t || !rho || !t_dust || n_stars < 0 || (n_stars > 0 && !stars))
+        return tr_fail(ctx, TR_EINVAL, "tr_tree_refill: bad argument");
+    if (!t->src || !t->s64[0]) return tr_fail(ctx, TR_EINVAL, "tr_tree_refill: tree has no refill buffers");
+    TR_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int TPB = 256;
+    const int64_t n = t->n_node, nc = t->n_cells;
+    Scratch64 S64 = {t->s64[0], t->s64[1], t->s64[2], t->s64[3], t->s64[4], t->s64[5]};
+    k_zero_f64<<<tr_div_up(nc, TPB), TPB, 0, st>>>(t->src, nc);
+    if (n_stars > 0)
+        k_stars<<<1, 64, 0, st>>>(reinterpret_cast<const double4 *>(stars), n_stars, t->n_fine, t->x0[0],
+                                  t->x0[1], t->x0[2], t->box_len / (double)t->n_fine, t->u_len * t->u_len,
+                                  t->geo, t->meta, t->leaf_cell, t->src);
+    k_leaf_fill<<<tr_div_up(nc, TPB), TPB, 0, st>>>(nc, rho, kappa, t_dust, t->src, t->node_of_cell, t->meta,
+                                                    t->root_edge, t->u_len, t->sigma, S64, t->q, t->vthick,
+                                                    t->cell_tau, t->cell_kappa, t->cell_src);
+    for (int d = t->D - 1; d >= 0; --d) {
+        int64_t lo = t->depth_off[d], hi = t->depth_off[d + 1];
+        if (hi > lo)
+            k_up<<<tr_div_up(hi - lo, TPB), TPB, 0, st>>>(lo, hi, t->geo, t->meta, S64, t->q, t->vthick, t->pcol);
+    }
+    k_pack<<<tr_div_up(n, TPB), TPB, 0, st>>>(n, t->geo, t->meta, t->packed);
+    return hipGetLastError() == hipSuccess ? TR_OK : tr_fail(ctx, TR_EHIP, "tr_tree_refill: launch failed");
 }
 
 extern "C" int tr_tree_get_info(const tr_tree *t, tr_tree_info *info) {
