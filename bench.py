@@ -402,8 +402,17 @@ def ray_count_study(name):
             best = min(best, e0.elapsed_time(e1))
         ctx.sync()
         tj[ns] = (np.pi * np.maximum(J.cpu().numpy().astype(np.float64), 0) / w.units[0]) ** 0.25
+        # accepted nodes per target (the walk counters): the opening angle follows the ray
+        # count, so the work per target grows faster than the rays
+        cnt = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
+        T.walk_counts(ctx, tree, p, cnt)
+        ctx.sync()
+        acc = float(cnt[:, :2].to(torch.float64).sum().item()) / n
+        del cnt
         res[ns] = {"rays": 12 * ns * ns, "trace_ms": round(best, 3),
-                   "target_rays_per_s": n * 12 * ns * ns / (best / 1000.0)}
+                   "target_rays_per_s": n * 12 * ns * ns / (best / 1000.0),
+                   "accepted_nodes_per_target": round(acc, 1),
+                   "ns_per_accepted_node_and_target": round(best * 1e6 / (acc * n), 4)}
         log(f"ray study {name}: N_side {ns}: {best:.1f} ms")
     x = W.synth.cell_centres(w)
     c = np.asarray(w.x0) + 0.5 * w.box_len
@@ -415,6 +424,8 @@ def ray_count_study(name):
     base = res[2]["trace_ms"]
     out = {"study": "ray count", "workload": f"{name}: {WORKLOADS[name]}", "n_cells": n,
            "cost_ratio_48_192_768": [round(res[k]["trace_ms"] / base, 3) for k in (2, 4, 8)],
+           "accepted_node_ratio_48_192_768": [round(res[k]["accepted_nodes_per_target"] /
+                                                    res[2]["accepted_nodes_per_target"], 3) for k in (2, 4, 8)],
            "paper_cost_ratio_48_192_768": [1.0, 4.39, 15.98],
            "paper_t_j_residual_vs_768_half": {"48": "-15.4% +- 14%", "192": "-3.77% +- 5.31%"},
            "paper_t_j_residual_vs_768_full": {"48": "-31.0% +- 17.9%", "192": "-13.2% +- 10.5%"},
@@ -612,6 +623,22 @@ def main():
         tr.free()
     tree = trees[-1]
     ms = (t1 - t0) * 1000.0 / args.steps
+
+    # the allocation-free refill of the same tree (what a graph-captured step runs in place of
+    # the build); reported beside the step, which keeps the build
+    st_dev = (torch.from_numpy(np.ascontiguousarray(np.asarray(w.stars, np.float64).reshape(-1, 4)))
+              .cuda() if len(w.stars) else None)
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tree.refill(dev["rho"], dev["kappa"], dev["t_dust"], st_dev)
+    refill_ms = []
+    for i in range(3):
+        r0.record()
+        tree.refill(dev["rho"], dev["kappa"], dev["t_dust"], st_dev)
+        r1.record()
+        torch.cuda.synchronize()
+        refill_ms.append(r0.elapsed_time(r1))
+    ctx.sync()
+    times["refill"] = refill_ms
     value = n * n_pix / (ms / 1000.0)
     log(f"timed {args.steps} steps: {ms:.1f} ms per step")
 
