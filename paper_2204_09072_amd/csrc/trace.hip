@@ -506,8 +506,10 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
     };
     if (FAR) {
         // tabulated entries: slot t holds the t-th pixel, count 0 = unused (slots are filled
-        // from 0), so the slot index is the same on every lane.  Every lane has a slot 0;
-        // later slots are sparse and go to the bins directly.
+        // from 0), so the slot index is the same on every lane.  Every lane has a slot 0 and
+        // most have a slot 1 (far nodes of classes 6-8 reach 1.6-2.1 pixels), and siblings in
+        // neighbouring lanes often share those bins: both take the run sums.  Slots 2 and 3
+        // are sparse and go to the bins directly.
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const uint32_t ct = tab ? (counts >> (8 * t)) & 255u : 0u;
@@ -516,7 +518,7 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
             float v0, v1;
             const float al = (1.0f / 64.0f) * (float)ct;
             update(ct != 0u, pix[t], al, al * beta, key, v0, v1);
-            if (t == 0) {
+            if (t <= 1) {
                 flush(key, v0, v1);
             } else if (key >= 0 && (v0 != 0.0f || v1 != 0.0f)) {
                 float *bb = bins + key * kThin;
