@@ -84,7 +84,7 @@ void tr_tree_free(tr_tree *tree);
  * App. A h-nodes and centres of luminosity): the same node arrays as tr_build_tree of the same
  * grid with these inputs, bit for bit, without allocating or synchronising, so it can be
  * captured in a graph with the calls that follow it.  rho, kappa (or NULL), t_dust as in
- * tr_build_tree; stars: DEVICE array of n_stars tr_star (NULL when n_stars = 0).  The units
+ * tr_build_tree; stars: DEVICE array of n_stars tr_star, 8-byte aligned (NULL when n_stars = 0).  The units
  * are the build's; no input validation.  Asynchronous. */
 int tr_tree_refill(tr_ctx *ctx, tr_tree *tree, const float *rho, const float *kappa,
                    const float *t_dust, const tr_star *stars, int n_stars);

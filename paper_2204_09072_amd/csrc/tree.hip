@@ -131,14 +131,15 @@ __global__ void k_cells(const int4 *__restrict__ blocks, int64_t n_cells, int D,
 // cell is the leaf holding its fine cell floor((x - x0) / dx_min) (half-open, clamped to the
 // grid), found by descending from the root: at each node the octant of the fine cell's
 // centre 2 f + 1 (in u) against the node's centre, then that child among the existing ones.
-__global__ void k_stars(const double4 *__restrict__ stars, int n_star, int64_t n_fine, double x0,
+__global__ void k_stars(const double *__restrict__ stars, int n_star, int64_t n_fine, double x0,
                         double y0, double z0, double dxmin, double u2, const int4 *__restrict__ geo,
                         const uint32_t *__restrict__ meta, const int32_t *__restrict__ leaf_cell,
                         double *__restrict__ src) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     for (int s = 0; s < n_star; ++s) {
-        double4 st = stars[s];
-        double pos[3] = {st.x - x0, st.y - y0, st.z - z0};
+        // (x, y, z, L) read as four doubles: a caller's array needs only 8-byte alignment
+        const double *st = stars + 4 * (int64_t)s;
+        double pos[3] = {st[0] - x0, st[1] - y0, st[2] - z0};
         int64_t c[3];
         for (int a = 0; a < 3; ++a) {
             double q = floor(pos[a] / dxmin);
@@ -151,7 +152,7 @@ __global__ void k_stars(const double4 *__restrict__ stars, int n_star, int64_t n
             const uint32_t m = meta[id];
             if (m & (1u << 12)) {
                 const int cell = leaf_cell[id];
-                src[cell] = src[cell] + st.w / u2;
+                src[cell] = src[cell] + st[3] / u2;
                 break;
             }
             const int4 g = geo[id];
@@ -470,7 +471,7 @@ extern "C" int tr_build_tree(tr_ctx *ctx, const tr_grid *grid, const float *rho,
             cleanup(); return tr_fail(ctx, TR_EHIP, "star upload failed");
         }
         double dxmin = grid->box_len / (double)n_fine;
-        k_stars<<<1, 64, 0, st>>>(d_stars, n_stars, n_fine, grid->x0[0], grid->x0[1], grid->x0[2], dxmin,
+        k_stars<<<1, 64, 0, st>>>(reinterpret_cast<const double *>(d_stars), n_stars, n_fine, grid->x0[0], grid->x0[1], grid->x0[2], dxmin,
                                   t->u_len * t->u_len, t->geo, t->meta, t->leaf_cell, src);
     }
     k_leaf_fill<<<tr_div_up(nc, TPB), TPB, 0, st>>>(nc, rho, kappa, t_dust, src, t->node_of_cell, t->meta,
@@ -510,7 +511,7 @@ extern "C" int tr_tree_refill(tr_ctx *ctx, tr_tree *t, const float *rho, const f
     Scratch64 S64 = {t->s64[0], t->s64[1], t->s64[2], t->s64[3], t->s64[4], t->s64[5]};
     k_zero_f64<<<tr_div_up(nc, TPB), TPB, 0, st>>>(t->src, nc);
     if (n_stars > 0)
-        k_stars<<<1, 64, 0, st>>>(reinterpret_cast<const double4 *>(stars), n_stars, t->n_fine, t->x0[0],
+        k_stars<<<1, 64, 0, st>>>(reinterpret_cast<const double *>(stars), n_stars, t->n_fine, t->x0[0],
                                   t->x0[1], t->x0[2], t->box_len / (double)t->n_fine, t->u_len * t->u_len,
                                   t->geo, t->meta, t->leaf_cell, t->src);
     k_leaf_fill<<<tr_div_up(nc, TPB), TPB, 0, st>>>(nc, rho, kappa, t_dust, t->src, t->node_of_cell, t->meta,
