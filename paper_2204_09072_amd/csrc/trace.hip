@@ -544,14 +544,22 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
     }
 }
 
-template <int NSLOT>
+// A ray's state between passes: sum of the thin optical depths of its closed inner segments,
+// thick extinction, flux so far and the first point of its open (merged) segment (0 = none;
+// that segment's content waits in the wave's carry slots).  It lives in the wave's workspace
+// as one float4 per ray (tau, eps, F, run as int bits): in registers it would hold 4 of them
+// per ray slot for the whole walk, 48 at 768 rays.
 struct RayState {
-    float tau_thin[NSLOT]; // sum of thin optical depths of closed inner segments
-    float eps_thick[NSLOT];
-    float Fh[NSLOT];
-    int run_i[NSLOT];      // first point of the open (merged) segment, 0 = none; its content
-                           // waits in the wave's global carry slots between passes
+    float tau_thin, eps_thick, Fh;
+    int run_i;
 };
+__device__ __forceinline__ RayState ray_load(const float4 *rs) {
+    const float4 v = *rs;
+    return RayState{v.x, v.y, v.z, __float_as_int(v.w)};
+}
+__device__ __forceinline__ void ray_store(float4 *rs, const RayState &R) {
+    *rs = make_float4(R.tau_thin, R.eps_thick, R.Fh, __int_as_float(R.run_i));
+}
 
 // One closed segment at R_i (Sec. 4.3.1, 4.3.2): updates the ray's flux and extinction.
 __device__ __forceinline__ void integrate_segment(const float *s, int i, float omega, float &tau_thin,
@@ -621,13 +629,13 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     int wtx = tx, wty = ty, wtz = tz, wtid = tid;
     asm volatile("" : "+v"(wtx), "+v"(wty), "+v"(wtz), "+v"(wtid));
     const int orient = __builtin_amdgcn_readfirstlane(target_orient(A.orient, A.orient_seed, A.leaf_cell[tid]));
-    RayState<NSLOT> R;
+    // the wave's workspace: [npix][bp] thick accumulators, [npix][2] carry slots, then the
+    // ray states, [NSLOT][64]; all of it is zero whenever no target is being traced
+    float4 *rs = COUNT ? nullptr : thick + A.npix * (A.bp + 2);
+    if (!COUNT) {
 #pragma unroll
-    for (int k = 0; k < NSLOT; ++k) {
-        R.tau_thin[k] = 0.0f;
-        R.eps_thick[k] = 1.0f;
-        R.Fh[k] = 0.0f;
-        R.run_i[k] = 0;
+        for (int k = 0; k < NSLOT; ++k)
+            if (lane + 64 * k < A.npix) rs[k * 64 + lane] = make_float4(0.0f, 1.0f, 0.0f, 0.0f);
     }
     int n_b = 0, n_h = 0, n_open = 0;
     const int n_pass = COUNT ? 1 : A.n_pass;
@@ -796,12 +804,13 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
         for (int sl = 0; sl < NSLOT; ++sl) {
             const int h = lane + 64 * sl;
             if (h >= A.npix) continue;
+            RayState R = ray_load(rs + sl * 64 + lane);
             const bool half = A.bp <= 8;
             const uint32_t fl = half ? (flg[h >> 1] >> ((h & 1) << 4)) & 0xffffu : flg[h];
             const int tsh = half ? 8 : 16;
             float4 *carry = thick + A.npix * A.bp + 2 * h;
             float acc[kFields] = {0, 0, 0, 0, 0, 0};
-            if (R.run_i[sl] != 0) {
+            if (R.run_i != 0) {
                 // take the carried content and clear the slots: the accumulator memory is
                 // all-zero whenever no target is being traced
                 const float4 c0 = carry[0], c1 = carry[1];
@@ -818,13 +827,13 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
 #pragma unroll
                     for (int f = 0; f < 4; ++f) v[2 + f] = atomicExch(tk + f, 0.0f);
                 }
-                if (R.run_i[sl] == 0) {
-                    R.run_i[sl] = i;
+                if (R.run_i == 0) {
+                    R.run_i = i;
 #pragma unroll
                     for (int f = 0; f < kFields; ++f) acc[f] = v[f];
                 } else {
                     // inverse-square content moves to the merged segment's R_i
-                    const float T = (float)R.run_i[sl] * rcp((float)i);
+                    const float T = (float)R.run_i * rcp((float)i);
                     const float T4 = (T * T) * (T * T);
                     acc[0] += T4 * v[0];
                     acc[1] += T4 * v[1];
@@ -835,15 +844,16 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                 }
                 const bool link = ((fl >> (i - P.a)) & 1u) && i < A.n_bins;
                 if (!link) {
-                    integrate_segment(acc, R.run_i[sl], A.omega, R.tau_thin[sl], R.eps_thick[sl], R.Fh[sl]);
-                    R.run_i[sl] = 0;
+                    integrate_segment(acc, R.run_i, A.omega, R.tau_thin, R.eps_thick, R.Fh);
+                    R.run_i = 0;
                 }
             }
-            if (R.run_i[sl] != 0) {
+            if (R.run_i != 0) {
                 // a merged segment still open at the pass end continues in the next pass
                 carry[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
                 carry[1] = make_float4(acc[4], acc[5], 0.0f, 0.0f);
             }
+            ray_store(rs + sl * 64 + lane, R);
         }
         wave_sync();
     }
@@ -867,7 +877,9 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     for (int sl = 0; sl < NSLOT; ++sl) {
         const int h = lane + 64 * sl;
         if (h >= A.npix) continue;
-        const float Fh = R.Fh[sl] + __expf(-R.tau_thin[sl]) * R.eps_thick[sl] * A.omega * A.j_bg;
+        const RayState R = ray_load(rs + sl * 64 + lane);
+        rs[sl * 64 + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f); // the workspace back to zero
+        const float Fh = R.Fh + __expf(-R.tau_thin) * R.eps_thick * A.omega * A.j_bg;
         const float4 n = A.dirs[h];
         js += Fh;
         fx -= Fh * n.x;
@@ -896,8 +908,11 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     }
 }
 
+// wide rays (12 per lane): three waves per SIMD, which the ray states' leaving the registers
+// allows (168 VGPRs)
 template <int NSLOT, bool COUNT, bool LDS_TABLE>
-__global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
+__global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) __attribute__((amdgpu_waves_per_eu(NSLOT > 3 ? 3 : 1)))
+void k_trace(TraceArgs A) {
     extern __shared__ __align__(16) char smem[];
     const uint8_t *tab8 = reinterpret_cast<const uint8_t *>(smem);
     const int ncell = 6 << (2 * A.log2m);
@@ -910,7 +925,8 @@ __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace(TraceArgs A) {
     }
     char *lds = smem + A.lds_table + (threadIdx.x >> 6) * A.lds_wave;
     float4 *thick = COUNT ? nullptr
-                          : A.thick + (int64_t)(blockIdx.x * A.per_block + (threadIdx.x >> 6)) * A.npix * (A.bp + 2);
+                          : A.thick + (int64_t)(blockIdx.x * A.per_block + (threadIdx.x >> 6)) *
+                                          (A.npix * (A.bp + 2) + 64 * NSLOT);
     // XCD-aware work distribution: blocks are dispatched round-robin over the 8 XCDs, so
     // block b runs on XCD b % 8; each XCD takes targets from its own contiguous range of
     // the (Morton-ordered) target list and keeps that region of the tree in its L2.  A
@@ -960,7 +976,8 @@ struct BatchArgs {
 };
 
 template <int NSLOT, bool LDS_TABLE>
-__global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) void k_trace_batch(BatchArgs B) {
+__global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) __attribute__((amdgpu_waves_per_eu(NSLOT > 3 ? 3 : 1)))
+void k_trace_batch(BatchArgs B) {
     extern __shared__ __align__(16) char smem[];
     if (LDS_TABLE) {
         for (int s = 0; s < B.n_tab; ++s) {
@@ -1046,13 +1063,14 @@ constexpr int kLdsCu = 160 * 1024;
 int table_bytes(int M) { return (6 * M * M + 15) & ~15; }
 int max_waves_for(int npix) { return npix > 192 ? 4 : 16; } // the kernel's launch bound
 // waves a CU should hold at once; passes are sized so that this many waves share the CU's
-// LDS.  Wide rays (~190 VGPRs, two waves per SIMD): 8 (128^3 core, 2 segments per pass and
-// 8 waves 13.6 s, 4 and 4 waves 23.3 s).  Otherwise 16, four per SIMD, the most the
-// registers allow.  Each pass re-walks the tree, so the LDS left beside the bins decides
-// the walk's cost: with two rays per flag word and no far-node offsets in the queue, the
-// 128^3 core and the AMR 256^3-equivalent tree take 4 segments per pass at 16 waves (1.39 s
-// and 1.91 s, against 1.42 s and 2.00 s with 3).
-int waves_cu_for(int npix) { return npix > 192 ? 8 : 16; }
+// LDS.  Wide rays (168 VGPRs, three waves per SIMD): 12, one segment per pass on the 128^3
+// core (8.8 s, against 10.6 s for 2 segments and 8 waves, which the registers allowed
+// before the ray states left them).  Otherwise 16, four per SIMD, the most the registers
+// allow.  Each pass re-walks the tree, so the LDS left beside the bins decides the walk's
+// cost: with two rays per flag word and no far-node offsets in the queue, the 128^3 core
+// and the AMR 256^3-equivalent tree take 4 segments per pass at 16 waves (1.39 s and
+// 1.91 s, against 1.42 s and 2.00 s with 3).
+int waves_cu_for(int npix) { return npix > 192 ? 12 : 16; }
 int nslot_for(int npix) { return npix <= 64 ? 1 : (npix <= 192 ? 3 : 12); }
 // the one-wave kernels keep the pixel table in LDS for up to 64 rays (N_side <= 2, at most
 // 6 KB); beyond that only near nodes read it, from global memory, and the LDS holds more
@@ -1185,7 +1203,7 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     const int grid = ctx->n_cu * blocks_cu;
     A.thick = nullptr;
     if (!count) {
-        rc = ensure_thick(ctx, (int64_t)grid * per_block * npix * (A.bp + 2));
+        rc = ensure_thick(ctx, (int64_t)grid * per_block * (npix * (A.bp + 2) + 64 * nslot_for(npix)));
         if (rc) return rc;
         A.thick = ctx->ws_thick;
     }
@@ -1251,6 +1269,7 @@ int batch_configure(tr_batch *b, Knobs k) {
         lds_wave = I.A.lds_wave > lds_wave ? I.A.lds_wave : lds_wave;
         thick_wave = I.npix * (I.A.bp + 2) > thick_wave ? I.npix * (I.A.bp + 2) : thick_wave;
     }
+    thick_wave += 64 * b->nslot; // the ray states
     int per_block = k.waves > 0 ? k.waves : (kLdsCu - b->lds_table) / lds_wave;
     if (per_block > max_waves) per_block = max_waves;
     if (per_block < 1) return tr_fail(ctx, TR_EINVAL, "batch: LDS too small for one wave (%d + %d bytes)",
