@@ -546,20 +546,52 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
 
 // A ray's state between passes: sum of the thin optical depths of its closed inner segments,
 // thick extinction, flux so far and the first point of its open (merged) segment (0 = none;
-// that segment's content waits in the wave's carry slots).  It lives in the wave's workspace
-// as one float4 per ray (tau, eps, F, run as int bits): in registers it would hold 4 of them
-// per ray slot for the whole walk, 48 at 768 rays.
+// that segment's content waits in the wave's carry slots).
 struct RayState {
     float tau_thin, eps_thick, Fh;
     int run_i;
 };
-__device__ __forceinline__ RayState ray_load(const float4 *rs) {
-    const float4 v = *rs;
-    return RayState{v.x, v.y, v.z, __float_as_int(v.w)};
-}
-__device__ __forceinline__ void ray_store(float4 *rs, const RayState &R) {
-    *rs = make_float4(R.tau_thin, R.eps_thick, R.Fh, __int_as_float(R.run_i));
-}
+
+// The wave's ray states.  Up to 3 rays per lane they stay in registers.  Wide rays (12 per
+// lane, 48 registers of states held through the whole walk) keep them in the wave's
+// workspace after the thick accumulators and carry slots, one float4 per ray (tau, eps, F,
+// run as int bits), written back to zero when the target is done; that frees the registers
+// for three waves per SIMD.
+__host__ __device__ constexpr int ray_state_floats4(int nslot) { return nslot > 3 ? 64 * nslot : 0; }
+template <int NSLOT, bool MEM = (NSLOT > 3)>
+struct RayStates {
+    RayState r[NSLOT];
+    __device__ __forceinline__ void init(float4 *, int) {
+#pragma unroll
+        for (int k = 0; k < NSLOT; ++k) r[k] = RayState{0.0f, 1.0f, 0.0f, 0};
+    }
+    __device__ __forceinline__ RayState load(float4 *, int sl) const { return r[sl]; }
+    __device__ __forceinline__ void store(float4 *, int sl, const RayState &R) { r[sl] = R; }
+    __device__ __forceinline__ RayState take(float4 *, int sl) { return r[sl]; }
+};
+// (ws: the wave's ray-state area; nothing is held in registers between the calls)
+template <int NSLOT>
+struct RayStates<NSLOT, true> {
+    // only the rays that exist: the others' entries must stay zero
+    __device__ __forceinline__ void init(float4 *ws, int npix) {
+#pragma unroll
+        for (int k = 0; k < NSLOT; ++k)
+            if (k * 64 + lane_id() < npix) ws[k * 64 + lane_id()] = make_float4(0.0f, 1.0f, 0.0f, 0.0f);
+    }
+    __device__ __forceinline__ RayState load(float4 *ws, int sl) const {
+        const float4 v = ws[sl * 64 + lane_id()];
+        return RayState{v.x, v.y, v.z, __float_as_int(v.w)};
+    }
+    __device__ __forceinline__ void store(float4 *ws, int sl, const RayState &R) {
+        ws[sl * 64 + lane_id()] = make_float4(R.tau_thin, R.eps_thick, R.Fh, __int_as_float(R.run_i));
+    }
+    // the last read, which leaves the area zero
+    __device__ __forceinline__ RayState take(float4 *ws, int sl) {
+        const RayState R = load(ws, sl);
+        ws[sl * 64 + lane_id()] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return R;
+    }
+};
 
 // One closed segment at R_i (Sec. 4.3.1, 4.3.2): updates the ray's flux and extinction.
 __device__ __forceinline__ void integrate_segment(const float *s, int i, float omega, float &tau_thin,
@@ -630,13 +662,9 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     asm volatile("" : "+v"(wtx), "+v"(wty), "+v"(wtz), "+v"(wtid));
     const int orient = __builtin_amdgcn_readfirstlane(target_orient(A.orient, A.orient_seed, A.leaf_cell[tid]));
     // the wave's workspace: [npix][bp] thick accumulators, [npix][2] carry slots, then the
-    // ray states, [NSLOT][64]; all of it is zero whenever no target is being traced
-    float4 *rs = COUNT ? nullptr : thick + A.npix * (A.bp + 2);
-    if (!COUNT) {
-#pragma unroll
-        for (int k = 0; k < NSLOT; ++k)
-            if (lane + 64 * k < A.npix) rs[k * 64 + lane] = make_float4(0.0f, 1.0f, 0.0f, 0.0f);
-    }
+    // ray states of wide rays; all of it is zero whenever no target is being traced
+    RayStates<NSLOT> RS;
+    if (!COUNT) RS.init(thick + A.npix * (A.bp + 2), A.npix);
     int n_b = 0, n_h = 0, n_open = 0;
     const int n_pass = COUNT ? 1 : A.n_pass;
     for (int ps = 0; ps < n_pass; ++ps) {
@@ -804,7 +832,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
         for (int sl = 0; sl < NSLOT; ++sl) {
             const int h = lane + 64 * sl;
             if (h >= A.npix) continue;
-            RayState R = ray_load(rs + sl * 64 + lane);
+            RayState R = RS.load(thick + A.npix * (A.bp + 2), sl);
             const bool half = A.bp <= 8;
             const uint32_t fl = half ? (flg[h >> 1] >> ((h & 1) << 4)) & 0xffffu : flg[h];
             const int tsh = half ? 8 : 16;
@@ -853,7 +881,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                 carry[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
                 carry[1] = make_float4(acc[4], acc[5], 0.0f, 0.0f);
             }
-            ray_store(rs + sl * 64 + lane, R);
+            RS.store(thick + A.npix * (A.bp + 2), sl, R);
         }
         wave_sync();
     }
@@ -877,8 +905,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     for (int sl = 0; sl < NSLOT; ++sl) {
         const int h = lane + 64 * sl;
         if (h >= A.npix) continue;
-        const RayState R = ray_load(rs + sl * 64 + lane);
-        rs[sl * 64 + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f); // the workspace back to zero
+        const RayState R = RS.take(thick + A.npix * (A.bp + 2), sl);
         const float Fh = R.Fh + __expf(-R.tau_thin) * R.eps_thick * A.omega * A.j_bg;
         const float4 n = A.dirs[h];
         js += Fh;
@@ -908,8 +935,8 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     }
 }
 
-// wide rays (12 per lane): three waves per SIMD, which the ray states' leaving the registers
-// allows (168 VGPRs)
+// wide rays (12 per lane): three waves per SIMD, which their ray states' leaving the
+// registers allows (168 VGPRs)
 template <int NSLOT, bool COUNT, bool LDS_TABLE>
 __global__ __launch_bounds__(NSLOT > 3 ? 256 : 1024) __attribute__((amdgpu_waves_per_eu(NSLOT > 3 ? 3 : 1)))
 void k_trace(TraceArgs A) {
@@ -926,7 +953,7 @@ void k_trace(TraceArgs A) {
     char *lds = smem + A.lds_table + (threadIdx.x >> 6) * A.lds_wave;
     float4 *thick = COUNT ? nullptr
                           : A.thick + (int64_t)(blockIdx.x * A.per_block + (threadIdx.x >> 6)) *
-                                          (A.npix * (A.bp + 2) + 64 * NSLOT);
+                                          (A.npix * (A.bp + 2) + ray_state_floats4(NSLOT));
     // XCD-aware work distribution: blocks are dispatched round-robin over the 8 XCDs, so
     // block b runs on XCD b % 8; each XCD takes targets from its own contiguous range of
     // the (Morton-ordered) target list and keeps that region of the tree in its L2.  A
@@ -1203,7 +1230,7 @@ int launch_trace(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, float 
     const int grid = ctx->n_cu * blocks_cu;
     A.thick = nullptr;
     if (!count) {
-        rc = ensure_thick(ctx, (int64_t)grid * per_block * (npix * (A.bp + 2) + 64 * nslot_for(npix)));
+        rc = ensure_thick(ctx, (int64_t)grid * per_block * (npix * (A.bp + 2) + ray_state_floats4(nslot_for(npix))));
         if (rc) return rc;
         A.thick = ctx->ws_thick;
     }
@@ -1269,7 +1296,7 @@ int batch_configure(tr_batch *b, Knobs k) {
         lds_wave = I.A.lds_wave > lds_wave ? I.A.lds_wave : lds_wave;
         thick_wave = I.npix * (I.A.bp + 2) > thick_wave ? I.npix * (I.A.bp + 2) : thick_wave;
     }
-    thick_wave += 64 * b->nslot; // the ray states
+    thick_wave += ray_state_floats4(b->nslot); // the ray states of wide rays
     int per_block = k.waves > 0 ? k.waves : (kLdsCu - b->lds_table) / lds_wave;
     if (per_block > max_waves) per_block = max_waves;
     if (per_block < 1) return tr_fail(ctx, TR_EINVAL, "batch: LDS too small for one wave (%d + %d bytes)",
