@@ -178,3 +178,60 @@ def test_batch_full_size_c4_sampled(lib, ctx):
     b.free()
     for t in trees:
         t.free()
+
+
+def test_batch_with_wide_rays_matches_oracle(lib, ctx):
+    """A batch that runs the wide-ray kernel (an N_side = 8 instance, whose ray states live in
+    the wave's workspace) beside N_side 1 and 2 instances with fewer rays than its lanes
+    hold: every instance against the oracle, on two graph replays."""
+    import torch
+    from paper_2204_09072_amd.run import params_of, tree_of, upload
+    ws = [TREE_CASES["sphere16"](), W.c3_core128(n=16, n_side=8), TREE_CASES["turb32"]()]
+    trees, J, F = [], [], []
+    for w in ws:
+        say("wide batch instance", w.name, w.n_cells, "cells, n_side", w.n_side)
+        trees.append(tree_of(ctx, w, upload(w)))
+        J.append(torch.full((w.n_cells,), -1.0, device="cuda"))
+        F.append(torch.full((3, w.n_cells), -1.0, device="cuda"))
+    ref = [oracle.Tree(w).trace(oracle.params(w.n_side, theta=w.theta)) for w in ws]
+    b = lib.Batch(ctx, trees, [params_of(w) for w in ws], J, F, None)
+    for rep in range(2):
+        for x in J + F:
+            x.fill_(-1.0)
+        say("wide batch replay", rep)
+        b.launch()
+        ctx.sync()
+        for j, f, (Jo, Fo) in zip(J, F, ref):
+            _check_trace(j.cpu().numpy(), f.cpu().numpy().T, Jo, Fo)
+    b.free()
+    for t in trees:
+        t.free()
+
+
+def test_wide_rays_leave_the_workspace_clean(lib, ctx):
+    """The wave workspace (thick accumulators, carry slots, wide rays' states) is zero
+    between launches: a 192-ray trace gives the same bits before and after 768-ray and
+    12-ray traces on the same context."""
+    import torch
+    from paper_2204_09072_amd.run import params_of, tree_of, upload
+    w4 = W.c3_core128(n=32, n_side=4)
+    t4 = tree_of(ctx, w4, upload(w4))
+    J0 = torch.empty(w4.n_cells, device="cuda")
+    F0 = torch.empty((3, w4.n_cells), device="cuda")
+    lib.trace_rays(ctx, t4, params_of(w4), J0, F0, None)
+    ctx.sync()
+    ref = (J0.cpu().numpy().copy(), F0.cpu().numpy().copy())
+    for ns in (8, 1):
+        w = W.c3_core128(n=16, n_side=ns)
+        t = tree_of(ctx, w, upload(w))
+        say("workspace: N_side", ns)
+        J = torch.empty(w.n_cells, device="cuda")
+        F = torch.empty((3, w.n_cells), device="cuda")
+        lib.trace_rays(ctx, t, params_of(w), J, F, None)
+        ctx.sync()
+        t.free()
+    lib.trace_rays(ctx, t4, params_of(w4), J0, F0, None)
+    ctx.sync()
+    assert np.array_equal(J0.cpu().numpy().view(np.uint32), ref[0].view(np.uint32))
+    assert np.array_equal(F0.cpu().numpy().view(np.uint32), ref[1].view(np.uint32))
+    t4.free()
