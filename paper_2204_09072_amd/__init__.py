@@ -123,6 +123,19 @@ MLP_NPARAM = _lib.tr_mlp_n_params()
 MLP_HIDDEN = 64
 
 
+def _check_device(name, t, dtype, optional=False):
+    """A device array argument must be a contiguous GPU tensor of the given dtype: the
+    library dereferences it in kernels."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name}: required")
+    if isinstance(t, np.ndarray) or not getattr(t, "is_cuda", False):
+        raise TypeError(f"{name}: a GPU tensor is required (got {type(t).__name__})")
+    if str(t.dtype) != f"torch.{dtype}" or not t.is_contiguous():
+        raise TypeError(f"{name}: contiguous {dtype} required (got {t.dtype})")
+
+
 def _ptr(t):
     """Device (or host numpy) address of a buffer, None for None."""
     if t is None:
@@ -187,6 +200,11 @@ class Tree:
     def refill(self, rho, kappa, t_dust, stars=None):
         """tr_tree_refill: new cell fields (device float32) and stars (device float64 [n, 4]
         or None) on the same blocks; asynchronous, allocation-free."""
+        for name, t, dt in (("rho", rho, "float32"), ("kappa", kappa, "float32"), ("t_dust", t_dust, "float32"),
+                            ("stars", stars, "float64")):
+            _check_device(name, t, dt, optional=name in ("kappa", "stars"))
+        if stars is not None and (stars.dim() != 2 or stars.shape[1] != 4):
+            raise ValueError("stars: device float64 [n, 4] (x, y, z, L)")
         n = 0 if stars is None else int(stars.shape[0])
         self.ctx.check(_lib.tr_tree_refill(self.ctx.h, self.h, _ptr(rho), _ptr(kappa), _ptr(t_dust),
                                            _ptr(stars) if n else None, n))

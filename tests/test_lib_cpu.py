@@ -163,3 +163,19 @@ def test_tuning_cache_store_and_key(tmp_path):
     t2, hit2 = tuning.tune_cached(b2, path, key)
     assert hit2 and b2.searched == 0 and b2.applied == (0, 8, 2)
     assert tuning.load(path)[key]["widest_pass"] == 14
+
+
+def test_binding_rejects_host_arrays_for_device_arguments():
+    """The refill's arrays are dereferenced in kernels: the binding refuses host arrays and
+    wrong dtypes before anything reaches the library."""
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    import torch
+    import paper_2204_09072_amd as T
+    with pytest.raises(TypeError):
+        T._check_device("stars", np.zeros((1, 4)), "float64")
+    with pytest.raises(TypeError):
+        T._check_device("rho", torch.zeros(4), "float32")   # a host tensor
+    with pytest.raises(ValueError):
+        T._check_device("rho", None, "float32")
+    T._check_device("kappa", None, "float32", optional=True)
