@@ -115,6 +115,11 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// set bits of a wave-wide mask in the lanes below this one (two mbcnt instructions)
+__device__ __forceinline__ int count_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // element i of an array, addressed as the array's (uniform) base plus a 32-bit byte offset,
@@ -492,7 +497,7 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
         const int prev = dpp_shr<1>(key, -2);
         const bool head = rl == 0 || prev != key;
         const uint64_t hb = __ballot(head);
-        const int rid = __builtin_popcountll(hb & ((2ull << lane) - 1ull));
+        const int rid = count_below(hb) + (head ? 1 : 0);
         seg_sum_step<1>(rl, rid, v0, v1);
         seg_sum_step<2>(rl, rid, v0, v1);
         seg_sum_step<4>(rl, rid, v0, v1);
@@ -784,9 +789,8 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                              (far1 ? (uint32_t)(c < kAlphaMax ? c : kAlphaMax) << 24 : 0u);
                     }
                 }
-                const uint64_t below = (1ull << lane) - 1ull;
                 const uint64_t bal = __ballot(open);
-                const int pos = __builtin_popcountll(bal & below);
+                const int pos = count_below(bal);
                 const int npush = __builtin_popcountll(bal);
                 if (open && sp + pos < A.kstack) stk[sp + pos] = push;
                 // an overflow drops the pushes past the stack and is reported once per pass
@@ -795,8 +799,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                 if (!COUNT) {
                     const uint64_t fb = __ballot(enq && far1), gb = __ballot(enq && !far1);
                     if (enq) {
-                        const int qp = far1 ? qf + __builtin_popcountll(fb & below)
-                                             : kQueue - 1 - qs - __builtin_popcountll(gb & below);
+                        const int qp = far1 ? qf + count_below(fb) : kQueue - 1 - qs - count_below(gb);
                         qnode[qp] = node;
                         qpk[qp] = pk;
                     }
