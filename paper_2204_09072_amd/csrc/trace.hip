@@ -683,6 +683,9 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
         const bool last = P.b > A.n_bins;
         const bool narrow = P.b - P.a <= 4;
         const PassT PT = pass_thresholds(P.a, P.b);
+        // the walk's per-lane comparisons take these from vector registers
+        int wa4 = a4, wb4 = b4;
+        asm volatile("" : "+v"(wa4), "+v"(wb4));
         if (!COUNT) {
             const int nf = A.npix * A.bp * kThin;
             for (int k = lane; k < nf; k += 64) bins[k] = 0.0f;
@@ -762,7 +765,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
                     open = opn & keep;
                     push = ((uint32_t)nd.w << 3) | (uint32_t)(__builtin_popcount((nd.y >> 16) & 255) - 1);
                     if (!COUNT) {
-                        const bool maybe = acc & (rmax2 >= a4) & (last | (rmin2 < b4));
+                        const bool maybe = acc & (rmax2 >= wa4) & (last | (rmin2 < wb4));
                         const int dx = leaf ? vx * TR_FX : pfc.x - c256.x;
                         const int dy = leaf ? vy * TR_FX : pfc.y - c256.y;
                         const int dz = leaf ? vz * TR_FX : pfc.z - c256.z;
