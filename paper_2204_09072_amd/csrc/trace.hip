@@ -683,7 +683,8 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
         const bool last = P.b > A.n_bins;
         const bool narrow = P.b - P.a <= 4;
         const PassT PT = pass_thresholds(P.a, P.b);
-        // the walk's per-lane comparisons take these from vector registers
+        // vector copies of the pass's radial bounds for the walk's per-lane test: as scalars
+        // they would come back from spill lanes every step
         int wa4 = a4, wb4 = b4;
         asm volatile("" : "+v"(wa4), "+v"(wb4));
         if (!COUNT) {
