@@ -144,3 +144,38 @@ def test_whole_step_in_one_graph(lib, ctx):
             del g
     finally:
         ctx.set_stream(old)
+
+
+def test_batch_replay_after_refill(lib, ctx):
+    """A captured batch reads its trees' node arrays at every replay: after a refill of one
+    instance the next replay gives, bit for bit, what the same batch over a tree built
+    directly from the new fields gives."""
+    import torch
+    from paper_2204_09072_amd.run import params_of, tree_of, upload
+    wa, wb = TREE_CASES["turb32"](), TREE_CASES["amr_small"]()
+    wa2 = _other_fields(wa, seed=31)
+    da, db, da2 = upload(wa), upload(wb), upload(wa2)
+    ta, tb = tree_of(ctx, wa, da), tree_of(ctx, wb, db)
+    J = [torch.empty(w.n_cells, device="cuda") for w in (wa, wb)]
+    F = [torch.empty((3, w.n_cells), device="cuda") for w in (wa, wb)]
+    b = lib.Batch(ctx, [ta, tb], [params_of(wa), params_of(wb)], J, F, None)
+    b.launch()
+    ctx.sync()
+    say("batch after refill: refill and replay")
+    ta.refill(da2["rho"], da2["kappa"], da2["t_dust"], _dev_stars(wa2))
+    b.launch()
+    ctx.sync()
+    got = [j.cpu().numpy().copy() for j in J]
+    say("batch after refill: the same batch over a fresh build")
+    ta2 = tree_of(ctx, wa2, da2)
+    J2 = [torch.empty(w.n_cells, device="cuda") for w in (wa, wb)]
+    F2 = [torch.empty((3, w.n_cells), device="cuda") for w in (wa, wb)]
+    b2 = lib.Batch(ctx, [ta2, tb], [params_of(wa2), params_of(wb)], J2, F2, None)
+    b2.launch()
+    ctx.sync()
+    for g_, w_ in zip(got, J2):
+        assert np.array_equal(g_.view(np.uint32), w_.cpu().numpy().view(np.uint32))
+    b.free()
+    b2.free()
+    for t in (ta, tb, ta2):
+        t.free()
