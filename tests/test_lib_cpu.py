@@ -179,3 +179,46 @@ def test_binding_rejects_host_arrays_for_device_arguments():
     with pytest.raises(ValueError):
         T._check_device("rho", None, "float32")
     T._check_device("kappa", None, "float32", optional=True)
+
+
+def test_entry_points_refuse_null_handles():
+    """Every call that takes a context, tree, batch or network returns TR_EINVAL (-1) for a
+    null one before anything reaches the GPU (runs on a host without one)."""
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+    calls = {
+        "tr_build_tree": [None] * 9,
+        "tr_tree_refill": [None, None, None, None, None, None, 0],
+        "tr_trace_rays": [None] * 6,
+        "tr_walk_counts": [None] * 4,
+        "tr_rad_force": [None] * 5,
+        "tr_dust_equilibrium": [None, 0] + [None] * 7,
+        "tr_dust_equilibrium_noalloc": [None, 0] + [None] * 7,
+        "tr_dust_fixed_point": [None] * 10 + [1, 0.0] + [None] * 6,
+        "tr_trace_rays_batched": [None, 1] + [None] * 5,
+        "tr_batch_create": [None, 1] + [None] * 6,
+        "tr_batch_launch": [None],
+        "tr_batch_launch_eager": [None],
+        "tr_batch_tune": [None, 16, None],
+        "tr_batch_set_tuning": [None, None],
+        "tr_mlp_create": [None] * 4,
+        "tr_mlp_forward": [None, None, 0, None, None],
+        "tr_mlp_train_step": [None, None, 0, None, None, 0.0, None],
+        "tr_ray_tables": [None, 4, 64, None, None],
+        "tr_alpha_table": [None, 4, 64, None],
+        "tr_star_luminosity_split": [None, 0, None, None, None, 0.1, 1.0, 1.0, None, None],
+        "tr_uv_rad_pressure": [None, 0] + [None] * 7,
+        "tr_sync": [None],
+        "tr_ctx_set_stream": [None, None],
+        "tr_ctx_set_validation": [None, 1],
+        "tr_tree_get_info": [None, None],
+        "tr_tree_export": [None] * 8,
+    }
+    for name, args in calls.items():
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        conv = [ctypes.c_double(a) if isinstance(a, float) else (ctypes.c_int(a) if isinstance(a, int) else P(a))
+                for a in args]
+        assert f(*conv) == -1, name
