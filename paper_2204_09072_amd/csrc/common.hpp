@@ -24,6 +24,11 @@ struct RayTable {
     // own pixel only and are read from the pixel table
     unsigned long long *alpha = nullptr;
     int alpha_c1 = 21;
+    // per-node angular kernel of a leaf at an integer offset m (in its edges, |m_a| <= 7,
+    // [mx + 7][my + 7][mz + 7]) from a target of its own size: the pixel ids of its 2x2x2
+    // sub-points in ascending order (10 bits each, x: 0-2, y: 3-5, z: 6-7) and in w the
+    // mask of the first of each run of equal ids
+    int4 *near = nullptr;
 };
 
 struct tr_ctx {
@@ -88,5 +93,7 @@ int tr_fail(tr_ctx *ctx, int code, const char *fmt, ...);
     } while (0)
 
 int tr_get_table(tr_ctx *ctx, int n_side, int cube_m, RayTable **out);
+// fills rt.near (allocated here) on the context's stream; the trace's own direction cells
+int tr_build_near_table(tr_ctx *ctx, RayTable &rt, int log2m);
 
 static inline int64_t tr_div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -259,6 +259,7 @@ int tr_get_table(tr_ctx *ctx, int n_side, int cube_m, RayTable **out) {
         hipFree(rt.table);
         hipFree(rt.dirs);
         hipFree(rt.alpha);
+        hipFree(rt.near);
         hipFree(full);
         hipFree(c_own);
     };
@@ -303,6 +304,10 @@ int tr_get_table(tr_ctx *ctx, int n_side, int cube_m, RayTable **out) {
         return tr_fail(ctx, TR_EHIP, "tabulated angular kernel compaction failed");
     }
     rt.alpha_c1 = c1;
+    if (int rc = tr_build_near_table(ctx, rt, log2m)) {
+        cleanup();
+        return rc;
+    }
     ctx->tables[key] = rt;
     *out = &ctx->tables[key];
     return TR_OK;

@@ -70,6 +70,7 @@ extern "C" void tr_ctx_destroy(tr_ctx *c) {
         hipFree(kv.second.table);
         hipFree(kv.second.dirs);
         hipFree(kv.second.alpha);
+        hipFree(kv.second.near);
     }
     hipFree(c->d_ctl);
     hipFree(c->ws_guess);

@@ -50,6 +50,7 @@ struct TraceArgs {
     const int16_t *table;
     const unsigned long long *alpha; // tabulated angular kernel [6 M M][classes 6 .. alpha_c1 - 1]
     const float4 *dirs;
+    const int4 *near;    // per-node kernel of same-size leaves at offsets up to 7 edges
     int *work;
     int *err;
     float4 *thick;  // per wave: [npix][bp] thick content accumulators (all-zero between uses),
@@ -193,6 +194,19 @@ __device__ __forceinline__ void cswap(int &a, int &b) {
     const int lo = min(a, b), hi = max(a, b);
     a = lo;
     b = hi;
+}
+
+// sort 8 pixel ids (19-comparator network), then mark the first of each run of equal ids
+__device__ __forceinline__ void sort8_runs(int (&pix)[8], bool valid, uint32_t &starts) {
+    cswap(pix[0], pix[2]); cswap(pix[1], pix[3]); cswap(pix[4], pix[6]); cswap(pix[5], pix[7]);
+    cswap(pix[0], pix[4]); cswap(pix[1], pix[5]); cswap(pix[2], pix[6]); cswap(pix[3], pix[7]);
+    cswap(pix[0], pix[1]); cswap(pix[2], pix[3]); cswap(pix[4], pix[5]); cswap(pix[6], pix[7]);
+    cswap(pix[2], pix[4]); cswap(pix[3], pix[5]);
+    cswap(pix[1], pix[4]); cswap(pix[3], pix[6]);
+    cswap(pix[1], pix[2]); cswap(pix[3], pix[4]); cswap(pix[5], pix[6]);
+    starts = valid ? 1u : 0u;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) starts |= (valid && pix[k] != pix[k - 1] ? 1u : 0u) << k;
 }
 
 // Orientation of the ray set (Sec. 7.6 names different HEALPix orientations as the remedy
@@ -375,8 +389,8 @@ __device__ __forceinline__ float beta_of(int dx, int dy, int dz, int i) {
 // pixels.  Merge and thick-content flags go to the rays' flag words (flag_words).
 template <bool LDS_TABLE, bool FAR>
 __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid, const int *qnode, const uint32_t *qpk,
-                                          int pass_a, int4 c256, int orient, const uint8_t *tab8, float *bins,
-                                          uint32_t *flg, float4 *thick) {
+                                          int pass_a, int4 c256, int tdepth, int orient, const uint8_t *tab8,
+                                          float *bins, uint32_t *flg, float4 *thick) {
     uint32_t starts = 0;
     int pix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     float Lt = 0, At = 0, LVk = 0, Ak = 0, Vk = 0, beta = 0;
@@ -392,7 +406,8 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
         const int node = qnode[ev];
         const uint32_t pk = qpk[ev];
         const bool leaf = (pk >> 18) & 1u;
-        const int s = A.root_edge >> ((pk >> 19) & 15u);
+        const int depth = (int)((pk >> 19) & 15u);
+        const int s = A.root_edge >> depth;
         seg = valid ? (int)(pk & 63u) - 1 : -1;
         const uint32_t k0 = (pk >> 6) & 63u, k1 = (pk >> 12) & 63u;
         fbits = valid && k1 > k0 ? (k1 >= 32u ? 0xffffffffu : ((1u << k1) - 1u)) & ~((1u << k0) - 1u) : 0u;
@@ -447,22 +462,28 @@ __device__ __forceinline__ void map_queue(const TraceArgs &A, int e, bool valid,
         }
         if (FAR && !tab) orient_offset(orient, dx, dy, dz); // more than 4 pixels: the per-node kernel
         if (!tab) {
-            const int h = (TR_FX / 4) * s;
+            // A leaf of the target's own size lies a whole number of edges m away, and its
+            // sub-points' directions depend on m alone: near ones read their sorted pixels
+            // from a table instead of binning and sorting them here
+            const int sh = 8 + (31 - __clz(A.root_edge)) - depth;
+            const int mx = dx >> sh, my = dy >> sh, mz = dz >> sh;
+            const bool tabled = !FAR && ((pk >> 18) & 1u) && depth == tdepth && (uint32_t)(mx + 7) < 15u &&
+                                (uint32_t)(my + 7) < 15u && (uint32_t)(mz + 7) < 15u;
+            if (tabled) {
+                const int4 nt = at32(A.near, __mul24(mx + 7, 225) + __mul24(my + 7, 15) + (mz + 7));
+                pix[0] = nt.x & 1023; pix[1] = (nt.x >> 10) & 1023; pix[2] = (nt.x >> 20) & 1023;
+                pix[3] = nt.y & 1023; pix[4] = (nt.y >> 10) & 1023; pix[5] = (nt.y >> 20) & 1023;
+                pix[6] = nt.z & 1023; pix[7] = (nt.z >> 10) & 1023;
+                starts = valid ? (uint32_t)nt.w : 0u;
+            } else {
+                const int h = (TR_FX / 4) * s;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int cx = dx + ((k & 1) ? h : -h), cy = dy + ((k & 2) ? h : -h), cz = dz + ((k & 4) ? h : -h);
-                pix[k] = lookup(cube_cell(cx, cy, cz, A.log2m));
+                for (int k = 0; k < 8; ++k) {
+                    const int cx = dx + ((k & 1) ? h : -h), cy = dy + ((k & 2) ? h : -h), cz = dz + ((k & 4) ? h : -h);
+                    pix[k] = lookup(cube_cell(cx, cy, cz, A.log2m));
+                }
+                sort8_runs(pix, valid, starts);
             }
-            // sort the 8 pixel ids (19-comparator network), then mark runs of equal ids
-            cswap(pix[0], pix[2]); cswap(pix[1], pix[3]); cswap(pix[4], pix[6]); cswap(pix[5], pix[7]);
-            cswap(pix[0], pix[4]); cswap(pix[1], pix[5]); cswap(pix[2], pix[6]); cswap(pix[3], pix[7]);
-            cswap(pix[0], pix[1]); cswap(pix[2], pix[3]); cswap(pix[4], pix[5]); cswap(pix[6], pix[7]);
-            cswap(pix[2], pix[4]); cswap(pix[3], pix[5]);
-            cswap(pix[1], pix[4]); cswap(pix[3], pix[6]);
-            cswap(pix[1], pix[2]); cswap(pix[3], pix[4]); cswap(pix[5], pix[6]);
-            starts = valid ? 1u : 0u;
-#pragma unroll
-            for (int k = 1; k < 8; ++k) starts |= (valid && pix[k] != pix[k - 1] ? 1u : 0u) << k;
         }
     }
     // One update per (node, pixel); each loop runs as often as the busiest lane needs.  Thin
@@ -661,6 +682,7 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
     const int tx = __builtin_amdgcn_readfirstlane(tr.x & 0xffff), ty = __builtin_amdgcn_readfirstlane(tr.y & 0xffff),
               tz = __builtin_amdgcn_readfirstlane(tr.z);
     const int4 c256 = make_int4(tx * TR_FX, ty * TR_FX, tz * TR_FX, 0);
+    const int tdepth = __builtin_amdgcn_readfirstlane((tr.x >> 16) & 15);
     // copies in vector registers for the walk's per-lane differences and comparisons: as
     // scalars they outnumber the scalar registers and come back from spill lanes every step
     int wtx = tx, wty = ty, wtz = tz, wtid = tid;
@@ -817,14 +839,14 @@ __device__ void trace_target(int inst, int ti, char *lds, const uint8_t *tab8, f
             if (qf >= 64 || (sp == 0 && qf > 0)) {
                 const int nq = qf >= 64 ? 64 : qf;
                 const int e = qf - nq + (lane < nq ? lane : 0);
-                map_queue<LDS_TABLE, true>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick);
+                map_queue<LDS_TABLE, true>(A, e, lane < nq, qnode, qpk, P.a, c256, tdepth, orient, tab8, bins, flg, thick);
                 qf -= nq;
                 wave_sync();
             }
             if (qs >= 64 || (sp == 0 && qs > 0)) {
                 const int nq = qs >= 64 ? 64 : qs;
                 const int e = kQueue - qs + (lane < nq ? lane : 0);
-                map_queue<LDS_TABLE, false>(A, e, lane < nq, qnode, qpk, P.a, c256, orient, tab8, bins, flg, thick);
+                map_queue<LDS_TABLE, false>(A, e, lane < nq, qnode, qpk, P.a, c256, tdepth, orient, tab8, bins, flg, thick);
                 qs -= nq;
                 wave_sync();
             }
@@ -1145,6 +1167,7 @@ int setup_instance(tr_ctx *ctx, const tr_tree *t, const tr_trace_params *p, floa
     A.nodes = t->packed; A.q = t->q; A.pcol = t->pcol;
     A.targets = t->targets; A.leaf_cell = t->leaf_cell; A.cell_tau = t->cell_tau; A.cell_src = t->cell_src;
     A.table = I.rt->table; A.alpha = I.rt->alpha; A.alpha_c1 = I.rt->alpha_c1; A.dirs = I.rt->dirs;
+    A.near = I.rt->near;
     A.per_node = p->per_node_kernel ? 1 : 0;
     A.work = ctx->d_ctl; A.err = ctx->d_ctl + 16;
     A.J = J; A.F = F; A.u_rad = u_rad; A.counters = counters;
@@ -1265,7 +1288,40 @@ struct Knobs {
     int bp = 0, waves = 0, chunk = 0;
 };
 
+// Per-node angular kernel of the leaves of a target's own size within 7 edges of it
+// (RayTable::near), built with the mapping's own direction cells.  Offsets are in units of
+// one edge (s = 1): the direction cells of the sub-points d +- s/4 do not change when d and
+// s scale together, since the cell index is an exact quotient of two of their components.
+__global__ void k_near_table(int log2m, const int16_t *__restrict__ table, int4 *__restrict__ near) {
+    const int key = blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= 15 * 15 * 15) return;
+    const int mx = key / 225 - 7, my = (key / 15) % 15 - 7, mz = key % 15 - 7;
+    const int h = TR_FX / 4;
+    int pix[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int cx = TR_FX * mx + ((k & 1) ? h : -h), cy = TR_FX * my + ((k & 2) ? h : -h),
+                  cz = TR_FX * mz + ((k & 4) ? h : -h);
+        pix[k] = table[cube_cell(cx, cy, cz, log2m)];
+    }
+    uint32_t starts = 0;
+    sort8_runs(pix, true, starts);
+    near[key] = make_int4(pix[0] | (pix[1] << 10) | (pix[2] << 20), pix[3] | (pix[4] << 10) | (pix[5] << 20),
+                          pix[6] | (pix[7] << 10), (int)starts);
+}
+
 } // namespace
+
+int tr_build_near_table(tr_ctx *ctx, RayTable &rt, int log2m) {
+    const int n = 15 * 15 * 15;
+    if (hipMalloc(&rt.near, sizeof(int4) * n) != hipSuccess) {
+        rt.near = nullptr;
+        return tr_fail(ctx, TR_ENOMEM, "near-leaf pixel table");
+    }
+    k_near_table<<<tr_div_up(n, 256), 256, 0, ctx->stream>>>(log2m, rt.table, rt.near);
+    TR_HIP(ctx, hipGetLastError());
+    return TR_OK;
+}
 
 struct tr_batch {
     tr_ctx *ctx = nullptr;
